@@ -1,0 +1,159 @@
+/*
+ * qhvp.h - C ABI of the MI355X (gfx950) library that evaluates the
+ * Hilbert-Schmidt cost, its gradient and its Hessian-vector product for a
+ * brickwall circuit of two-qubit gates against a reference unitary, by
+ * sample-batched recursive state propagation on full statevectors.
+ *
+ * The method is that of arXiv 2604.20384 ("Hessian-vector products for
+ * tensor networks via recursive tangent-state propagation"): forward states
+ * and their tangents (Sec. II.C-E, Eq. fis / Eq. dfis), backward states and
+ * their tangents (Eq. bis / Eq. dbis), per-gate environments (Eq.
+ * environment) and their directional derivatives (Eq. overlap-hvp), the
+ * Hilbert-Schmidt post-processing of Alg. 2 and the empirical risk over
+ * Haar product states (Eq. costHS), with the Riemannian projections of
+ * App. F.
+ *
+ * Conventions
+ *   - Complex numbers are interleaved (re, im) doubles; 4x4 matrices are
+ *     row-major, G[i][j] with i the output index, i = 2*b_q + b_{q+1} for a
+ *     gate on qubits (q, q+1).
+ *   - Brickwall: layer l (0-based, first applied) has a gate on every pair
+ *     (q, q+1) with q = l (mod 2), q + 1 < n.  Gates are numbered layer by
+ *     layer, by increasing q inside a layer; qhvp_num_gates(n, L) of them.
+ *   - Statevector index x = sum_q b_q 2^(n-1-q) (qubit 0 most significant).
+ *   - A sample is n single-qubit states (amp|0>, amp|1>): psi_s = u_s0 (x) ... (x) u_s,n-1.
+ *   - Cost C = 1 - F with F = (1/N_s) sum_s |phi_s^dag G psi_s|^2 and
+ *     phi_s = U_ref psi_s (Eq. costHS).  grad and hvp are the complex
+ *     gradients of C (App. A convention: grad f = df/dx + i df/dy entry-wise),
+ *     i.e. dC[V] = Re sum_k Tr(grad_k^dag V_k) and hvp = D(grad C)[V].
+ *
+ * Ownership: the caller owns every pointer it passes.  Host arrays are read
+ * during the call only.  The device workspace passed to
+ * qhvp_problem_create is used until qhvp_problem_destroy; the library never
+ * frees it.  With a NULL workspace the library allocates (and later frees)
+ * its own.
+ *
+ * Errors: every entry point returns a qhvp_status, never aborts, and leaves
+ * its outputs untouched on error; qhvp_last_error() gives a message (per
+ * thread).  Arguments are validated before any device work is launched.
+ *
+ * Threading: one problem is used by one host thread at a time; calls on one
+ * problem are serialised on its stream.  Different problems (each on its
+ * own stream) may be used from different threads concurrently.
+ */
+#ifndef QHVP_H
+#define QHVP_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qhvp_ctx qhvp_ctx;
+typedef struct qhvp_problem qhvp_problem;
+
+typedef enum {
+  QHVP_OK = 0,
+  QHVP_ERR_INVALID = 1,     /* bad sizes, null pointers, non-finite input, non-unitary gate in Riemannian mode */
+  QHVP_ERR_NOMEM = 2,       /* workspace smaller than qhvp_workspace_bytes, or allocation failed */
+  QHVP_ERR_DEVICE = 3,      /* a HIP runtime call failed */
+  QHVP_ERR_UNSUPPORTED = 4  /* e.g. an HVP on a problem created without tangent storage */
+} qhvp_status;
+
+typedef enum {
+  QHVP_C128 = 0,      /* complex128 states, FP64 reductions */
+  QHVP_C64_ACC64 = 1  /* complex64 states and gates; products reduced in FP32 over one tile, FP64 beyond */
+} qhvp_precision;
+
+typedef enum {
+  QHVP_EUCLIDEAN = 0,  /* plain complex gradient / HVP (Alg. 2) */
+  QHVP_RIEMANNIAN = 1  /* projected onto the tangent space of U(4)^K (App. F); V is projected first */
+} qhvp_geometry;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int qhvp_version(void);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* qhvp_last_error(void);
+
+/* Number of gates K of an n-qubit, L-layer open brickwall (Sec. III), or -1 if n < 2 or L < 1. */
+int qhvp_num_gates(int n, int L);
+
+/* Create / destroy a context bound to HIP device `device`. */
+qhvp_status qhvp_ctx_create(int device, qhvp_ctx** out);
+void qhvp_ctx_destroy(qhvp_ctx* ctx);
+
+/*
+ * Device workspace (bytes) a problem needs.
+ *   ckpt_every > 0 : keep the states at every ckpt_every-th layer boundary and
+ *                    recompute the rest of a segment in the backward sweep
+ *                    (layer checkpointing; Alg. 1 keeps every state instead).
+ *   ckpt_every = 0 : keep the state at every pass boundary (no recomputation).
+ *   ckpt_every < 0 : segments of -ckpt_every passes.
+ *   with_tangent   : 1 to allow qhvp_hvp (stores the tangent states too).
+ * Returns 0 on invalid arguments.
+ */
+size_t qhvp_workspace_bytes(int n, int L, int L_ref, int n_samples, qhvp_precision prec,
+                            int ckpt_every, int with_tangent);
+
+/*
+ * Create a problem: n qubits, an L-layer ansatz, a reference brickwall U_ref of
+ * L_ref layers with gates `uref_gates` (K_ref*16 complex, host), and n_samples
+ * product states `samples` (n_samples*n*2 complex, host).  Computes the labels
+ * phi_s = U_ref psi_s on the device (Alg. 2 takes phi^[0] as input) and keeps
+ * them for every later call.  `d_workspace` (device, caller-owned, >=
+ * qhvp_workspace_bytes(...) bytes, 256-byte aligned) may be NULL.
+ * `hip_stream` is a hipStream_t (NULL = default stream).
+ */
+qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref,
+                                const double* uref_gates, const double* samples, int n_samples,
+                                qhvp_precision prec, int ckpt_every, int with_tangent,
+                                void* d_workspace, size_t ws_bytes, void* hip_stream,
+                                qhvp_problem** out);
+void qhvp_problem_destroy(qhvp_problem* p);
+
+/* Cost C and fidelity F for gates G (K*16 complex, host).  One forward sweep (Sec. III, single-pass overlap). */
+qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fidelity);
+
+/* Cost and gradient (K*16 complex, host) of C at G: forward sweep, then the backward
+ * sweep accumulating the environments (Eq. environment, Alg. 2 "postprocess gradient"). */
+qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom,
+                      double* cost, double* grad);
+
+/* Cost, gradient and HVP H(C)[V] (each K*16 complex, host) at G along V (K*16
+ * complex, host): Alg. 1 + Alg. 2 with tangent states. `grad` may be NULL. */
+qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom,
+                     double* cost, double* grad, double* hvp);
+
+/* Per-sample overlaps T_s and Omega_s = D(T_s)[V] (n_samples complex each, host) of
+ * the last cost/grad/hvp call (Omega is zero unless that call was an HVP). */
+qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega);
+
+/* Problem facts: n_passes is the number of gate passes per sweep of the ansatz. */
+qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size_t* ws_bytes,
+                              int* segments);
+
+/* Milliseconds spent on the device by the last call (HIP events around it). */
+double qhvp_last_device_ms(const qhvp_problem* p);
+
+/* ---- FP64 host utilities on gate vectors (App. F); all arrays K*16 complex ---- */
+
+/* out = P_G(X) = X/2 - G X^dag G / 2, gate by gate (Eq. projec). */
+qhvp_status qhvp_project(int K, const double* G, const double* X, double* out);
+
+/* out = P_G(hvp - V grad^dag G / 2 - G grad^dag V / 2), gate by gate (App. F), for tangent V. */
+qhvp_status qhvp_riemannian_hvp(int K, const double* G, const double* grad, const double* hvp,
+                                const double* V, double* out);
+
+/* Polar retraction out = U W^dag where G + xi = U S W^dag (the paper names no retraction). */
+qhvp_status qhvp_retract(int K, const double* G, const double* xi, double* out);
+
+/* Max over gates of ||G_k^dag G_k - I||_F. */
+double qhvp_unitarity_error(int K, const double* G);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QHVP_H */

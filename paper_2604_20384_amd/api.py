@@ -1,0 +1,199 @@
+"""Python binding of the qhvp C ABI: `Context` and `Problem`.
+
+Device memory for the workspace comes from PyTorch (so its peak HBM is
+visible to `torch.cuda.max_memory_allocated`), and the HIP stream is a torch
+stream; everything else is marshalling.  Arrays are numpy complex128 of
+shape (K, 4, 4) for gates / directions / results.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import check, dptr, lib
+
+PRECISIONS = {"c128": _lib.QHVP_C128, "c64": _lib.QHVP_C64_ACC64}
+
+
+def num_gates(n: int, L: int) -> int:
+    return lib.qhvp_num_gates(n, L)
+
+
+def workspace_bytes(n, L, L_ref, n_samples, precision="c128", ckpt_every=1, with_tangent=True) -> int:
+    return int(lib.qhvp_workspace_bytes(n, L, L_ref, n_samples, PRECISIONS[precision], ckpt_every,
+                                        1 if with_tangent else 0))
+
+
+def _c128(a, shape=None) -> np.ndarray:
+    if hasattr(a, "detach"):          # torch tensor
+        a = a.detach().cpu().numpy()
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+    if shape is not None and a.shape != shape:
+        raise ValueError(f"expected shape {shape}, got {a.shape}")
+    return a
+
+
+def _f64(a: np.ndarray) -> np.ndarray:
+    return a.view(np.float64)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        check(lib.qhvp_ctx_create(device, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib.qhvp_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+class Problem:
+    """One (U_ref, samples) problem on the device; cost / grad / hvp for any gates G.
+
+    n, L        : qubits and ansatz layers (K = num_gates(n, L) gates).
+    uref        : (K_ref, 4, 4) gates of the reference brickwall of L_ref layers.
+    samples     : (N_s, n, 2) single-qubit states of the product-state samples.
+    precision   : "c128" or "c64" (complex64 states, FP64 accumulation).
+    ckpt_every  : layer-checkpoint interval (0 = keep every pass boundary).
+    """
+
+    def __init__(self, n, L, uref, samples, L_ref=None, precision="c128", ckpt_every=1,
+                 with_tangent=True, device=0, stream=None, workspace="torch"):
+        import torch
+
+        self.n, self.L = int(n), int(L)
+        self.K = num_gates(n, L)
+        uref = _c128(uref)
+        if L_ref is None:
+            L_ref = self._layers_of(uref.shape[0])
+        self.L_ref = int(L_ref)
+        self.K_ref = num_gates(n, L_ref)
+        uref = _c128(uref, (self.K_ref, 4, 4))
+        samples = _c128(samples)
+        if samples.ndim != 3 or samples.shape[1:] != (n, 2):
+            raise ValueError(f"samples must have shape (N_s, {n}, 2)")
+        self.n_samples = samples.shape[0]
+        self.precision = precision
+        self.ctx = default_context(device)
+        self.device = device
+        self.ws_bytes = workspace_bytes(n, L, L_ref, self.n_samples, precision, ckpt_every, with_tangent)
+        if self.ws_bytes == 0:
+            raise ValueError("invalid problem shape")
+        self._ws = None
+        ws_ptr = None
+        if workspace == "torch":
+            self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=f"cuda:{device}")
+            ws_ptr = C.c_void_p(self._ws.data_ptr())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        check(lib.qhvp_problem_create(self.ctx.handle, n, L, L_ref, dptr(_f64(uref)), dptr(_f64(samples)),
+                                      self.n_samples, PRECISIONS[precision], ckpt_every,
+                                      1 if with_tangent else 0, ws_ptr, self.ws_bytes,
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(h)))
+        self.handle = h
+
+    def _layers_of(self, K_ref):
+        for Lr in range(1, 10000):
+            if num_gates(self.n, Lr) == K_ref:
+                return Lr
+        raise ValueError("cannot infer L_ref from the number of U_ref gates")
+
+    # ------------------------------------------------------------------
+    def cost(self, G):
+        G = _c128(G, (self.K, 4, 4))
+        c, f = C.c_double(), C.c_double()
+        check(lib.qhvp_cost(self.handle, dptr(_f64(G)), C.byref(c), C.byref(f)))
+        return c.value, f.value
+
+    def grad(self, G, riemannian=False):
+        G = _c128(G, (self.K, 4, 4))
+        g = np.empty((self.K, 4, 4), dtype=np.complex128)
+        c = C.c_double()
+        check(lib.qhvp_grad(self.handle, dptr(_f64(G)), int(riemannian), C.byref(c), dptr(_f64(g))))
+        return c.value, g
+
+    def hvp(self, G, V, riemannian=False):
+        G = _c128(G, (self.K, 4, 4))
+        V = _c128(V, (self.K, 4, 4))
+        g = np.empty((self.K, 4, 4), dtype=np.complex128)
+        h = np.empty((self.K, 4, 4), dtype=np.complex128)
+        c = C.c_double()
+        check(lib.qhvp_hvp(self.handle, dptr(_f64(G)), dptr(_f64(V)), int(riemannian), C.byref(c),
+                           dptr(_f64(g)), dptr(_f64(h))))
+        return c.value, g, h
+
+    def overlaps(self):
+        T = np.empty(self.n_samples, dtype=np.complex128)
+        O = np.empty(self.n_samples, dtype=np.complex128)
+        check(lib.qhvp_overlaps(self.handle, dptr(_f64(T)), dptr(_f64(O))))
+        return T, O
+
+    def info(self):
+        K, npass, seg = C.c_int(), C.c_int(), C.c_int()
+        ws = C.c_size_t()
+        check(lib.qhvp_problem_info(self.handle, C.byref(K), C.byref(npass), C.byref(ws), C.byref(seg)))
+        return {"K": K.value, "n_passes": npass.value, "ws_bytes": ws.value, "segments": seg.value}
+
+    @property
+    def last_device_ms(self) -> float:
+        return lib.qhvp_last_device_ms(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.qhvp_problem_destroy(self.handle)
+            self.handle = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- FP64 geometry utilities (App. F), computed in the library
+def project(G, X):
+    G, X = _c128(G), _c128(X)
+    out = np.empty_like(G)
+    check(lib.qhvp_project(G.shape[0], dptr(_f64(G)), dptr(_f64(X)), dptr(_f64(out))))
+    return out
+
+
+def riemannian_hvp(G, grad, hvp, V):
+    G, grad, hvp, V = _c128(G), _c128(grad), _c128(hvp), _c128(V)
+    out = np.empty_like(G)
+    check(lib.qhvp_riemannian_hvp(G.shape[0], dptr(_f64(G)), dptr(_f64(grad)), dptr(_f64(hvp)),
+                                  dptr(_f64(V)), dptr(_f64(out))))
+    return out
+
+
+def retract(G, xi):
+    G, xi = _c128(G), _c128(xi)
+    out = np.empty_like(G)
+    check(lib.qhvp_retract(G.shape[0], dptr(_f64(G)), dptr(_f64(xi)), dptr(_f64(out))))
+    return out
+
+
+def unitarity_error(G) -> float:
+    G = _c128(G)
+    return float(lib.qhvp_unitarity_error(G.shape[0], dptr(_f64(G))))

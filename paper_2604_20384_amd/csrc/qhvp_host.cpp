@@ -1,0 +1,759 @@
+// Host runtime of the qhvp C ABI (include/qhvp.h): pass planning, workspace
+// layout with layer checkpoints, the launch sequence of one cost / gradient /
+// HVP evaluation, and the FP64 post-processing of Alg. 2 and App. F.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/qhvp.h"
+#include "qhvp_internal.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+qhvp_status fail(qhvp_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(QHVP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define LAUNCH_TRY(expr)                                                                \
+  do {                                                                                  \
+    int e_ = (expr);                                                                    \
+    if (e_ != 0) return fail(QHVP_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString((hipError_t)e_)); \
+  } while (0)
+
+constexpr int kCoalesceBits = 4;   // always-active low index bits: runs of >= 16 amplitudes
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int num_gates(int n, int L) {
+  if (n < 2 || L < 1) return -1;
+  return ((L + 1) / 2) * (n / 2) + (L / 2) * ((n - 1) / 2);
+}
+
+// One brickwall layer -> passes.  Gates on qubits (q, q+1) touch statevector bits
+// lo = n-2-q and lo+1.  Greedy in increasing lo: the tile keeps the low
+// kCoalesceBits bits and adds each gate's two bits while it has room; the leftover
+// room is filled with the lowest unused bits (longer contiguous runs).
+void plan_layer(int n, int layer, int first_gate, std::vector<qhvp::PassDesc>& out) {
+  const int mbmax = std::min(n, qhvp::kMaxTileBits);
+  std::vector<int> qs;
+  for (int q = layer % 2; q + 1 < n; q += 2) qs.push_back(q);
+  // gate index of pair q in this layer
+  std::vector<std::pair<int, int>> gl;  // (lo bit, gate index)
+  for (size_t i = 0; i < qs.size(); ++i) gl.push_back({n - 2 - qs[i], first_gate + (int)i});
+  std::sort(gl.begin(), gl.end());
+  const int cb = std::min(kCoalesceBits, mbmax);
+  size_t i = 0;
+  while (i < gl.size()) {
+    std::vector<bool> act(n, false);
+    for (int b = 0; b < cb; ++b) act[b] = true;
+    int cnt = cb;
+    std::vector<int> gates;
+    while (i < gl.size() && (int)gates.size() < qhvp::kMaxGates) {
+      int lo = gl[i].first;
+      int add = (act[lo] ? 0 : 1) + (act[lo + 1] ? 0 : 1);
+      if (cnt + add > mbmax) break;
+      act[lo] = act[lo + 1] = true;
+      cnt += add;
+      gates.push_back(i);
+      ++i;
+    }
+    for (int b = 0; b < n && cnt < mbmax; ++b)
+      if (!act[b]) { act[b] = true; ++cnt; }
+    qhvp::PassDesc pd;
+    std::memset(&pd, 0, sizeof(pd));
+    pd.n = n;
+    pd.mb = cnt;
+    int ti = 0, ii = 0;
+    std::vector<int> tpos(n, -1);
+    for (int b = 0; b < n; ++b) {
+      if (act[b]) { pd.abit[ti] = b; tpos[b] = ti++; }
+      else pd.ibit[ii++] = b;
+    }
+    // gates keep their layer order (by increasing q, i.e. decreasing lo); they commute anyway
+    std::sort(gates.begin(), gates.end(), [&](int x, int y) { return gl[x].second < gl[y].second; });
+    pd.ng = (int)gates.size();
+    for (int g = 0; g < pd.ng; ++g) {
+      int lo = gl[gates[g]].first;
+      pd.gidx[g] = gl[gates[g]].second;
+      pd.tlo[g] = tpos[lo];
+      pd.thi[g] = tpos[lo + 1];
+    }
+    out.push_back(pd);
+  }
+}
+
+std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* layer_first_pass) {
+  std::vector<qhvp::PassDesc> passes;
+  int k = 0;
+  for (int l = 0; l < L; ++l) {
+    if (layer_first_pass) layer_first_pass->push_back((int)passes.size());
+    size_t before = passes.size();
+    plan_layer(n, l, k, passes);
+    for (size_t p = before; p < passes.size(); ++p) k += passes[p].ng;
+  }
+  if (layer_first_pass) layer_first_pass->push_back((int)passes.size());
+  return passes;
+}
+
+// Segments of the backward sweep (pass index ranges); each segment starts at a stored
+// checkpoint (pass 0's input is regenerated from the samples).
+std::vector<std::pair<int, int>> plan_segments(int n, int L, int ckpt_every) {
+  std::vector<int> lfp;
+  auto passes = plan_circuit(n, L, &lfp);
+  const int np = (int)passes.size();
+  std::vector<std::pair<int, int>> seg;
+  if (ckpt_every > 0) {
+    for (int l = 0; l < L; l += ckpt_every) {
+      int l1 = std::min(L, l + ckpt_every);
+      seg.push_back({lfp[l], lfp[l1]});
+    }
+  } else {
+    int c = ckpt_every == 0 ? 1 : -ckpt_every;
+    for (int p = 0; p < np; p += c) seg.push_back({p, std::min(np, p + c)});
+  }
+  return seg;
+}
+
+struct Layout {
+  size_t state_bytes = 0;   // one state set: N_s * 2^n amplitudes
+  int n_ckpt = 0;           // stored segment-start checkpoints (segments 1..J-1)
+  int n_seg = 0;            // in-segment boundary buffers (max segment length - 1)
+  int slot_states = 1;      // state sets per slot (2 with tangent)
+  int n_wg_max = 0;
+  int tiles_max = 0;
+  size_t off_phi0 = 0, off_slots = 0, off_small = 0, total = 0;
+  size_t slot_bytes = 0;
+  // small buffers (offsets from off_small)
+  size_t o_samples, o_gates, o_dirs, o_uref, o_tov, o_ovpart, o_envpart, o_env;
+};
+
+bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_every, int tangent,
+                 Layout& lay) {
+  if (n < 2 || n > qhvp::kMaxQubits || L < 1 || L_ref < 1 || Ns < 1) return false;
+  const size_t amp = prec == QHVP_C64_ACC64 ? 8 : 16;
+  const int K = num_gates(n, L), Kr = num_gates(n, L_ref);
+  auto seg = plan_segments(n, L, ckpt_every);
+  int maxlen = 0;
+  for (auto& s : seg) maxlen = std::max(maxlen, s.second - s.first);
+  lay.state_bytes = align_up((size_t)Ns * ((size_t)1 << n) * amp);
+  lay.slot_states = tangent ? 2 : 1;
+  lay.slot_bytes = lay.state_bytes * lay.slot_states;
+  lay.n_ckpt = (int)seg.size() - 1;
+  lay.n_seg = maxlen - 1;
+  const int mb = std::min(n, qhvp::kMaxTileBits);
+  lay.tiles_max = 1 << (n - mb);
+  lay.n_wg_max = qhvp::grid_size((long long)Ns * lay.tiles_max);
+  lay.off_phi0 = 0;
+  lay.off_slots = lay.state_bytes;
+  const int nslots = lay.n_ckpt + lay.n_seg + 1;   // + working / backward (a, b) slot
+  lay.off_small = lay.off_slots + (size_t)nslots * lay.slot_bytes;
+  size_t o = 0;
+  lay.o_samples = o; o = align_up(o + (size_t)Ns * n * 2 * amp);
+  lay.o_gates = o;   o = align_up(o + (size_t)K * 16 * amp);
+  lay.o_dirs = o;    o = align_up(o + (size_t)K * 16 * amp);
+  lay.o_uref = o;    o = align_up(o + (size_t)Kr * 16 * amp);
+  lay.o_tov = o;     o = align_up(o + (size_t)Ns * 4 * sizeof(double));
+  // overlap partials: the ansatz and U_ref plans share the tile count of their passes
+  lay.o_ovpart = o;  o = align_up(o + (size_t)Ns * lay.tiles_max * 4 * sizeof(double) * 2);
+  lay.o_envpart = o; o = align_up(o + (size_t)lay.n_wg_max * qhvp::kMaxGates * qhvp::kEnvVals * sizeof(double));
+  lay.o_env = o;     o = align_up(o + (size_t)K * qhvp::kEnvVals * sizeof(double));
+  lay.total = lay.off_small + o;
+  return true;
+}
+
+bool finite_all(const double* x, size_t cnt) {
+  for (size_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(x[i])) return false;
+  return true;
+}
+
+// ---- 4x4 complex helpers (FP64, host)
+typedef cd M4[16];
+void load4(const double* p, cd* m) { for (int i = 0; i < 16; ++i) m[i] = cd(p[2 * i], p[2 * i + 1]); }
+void store4(const cd* m, double* p) { for (int i = 0; i < 16; ++i) { p[2 * i] = m[i].real(); p[2 * i + 1] = m[i].imag(); } }
+void mul4(const cd* a, const cd* b, cd* c) {
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) {
+      cd s = 0;
+      for (int k = 0; k < 4; ++k) s += a[4 * i + k] * b[4 * k + j];
+      c[4 * i + j] = s;
+    }
+}
+void dag4(const cd* a, cd* b) { for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) b[4 * i + j] = std::conj(a[4 * j + i]); }
+// P_G(X) = X/2 - G X^dag G / 2 (Eq. projec)
+void project4(const cd* G, const cd* X, cd* out) {
+  M4 Xd, t, u;
+  dag4(X, Xd);
+  mul4(G, Xd, t);
+  mul4(t, G, u);
+  for (int i = 0; i < 16; ++i) out[i] = 0.5 * X[i] - 0.5 * u[i];
+}
+// P_G(H - V grad^dag G / 2 - G grad^dag V / 2) (App. F)
+void riem_hvp4(const cd* G, const cd* gr, const cd* H, const cd* V, cd* out) {
+  M4 grd, t1, t2, t3, t4, inner;
+  dag4(gr, grd);
+  mul4(V, grd, t1); mul4(t1, G, t2);
+  mul4(G, grd, t3); mul4(t3, V, t4);
+  for (int i = 0; i < 16; ++i) inner[i] = H[i] - 0.5 * t2[i] - 0.5 * t4[i];
+  project4(G, inner, out);
+}
+double unitarity_err4(const cd* G) {
+  M4 Gd, P;
+  dag4(G, Gd);
+  mul4(Gd, G, P);
+  double e = 0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j) e += std::norm(P[4 * i + j] - (i == j ? 1.0 : 0.0));
+  return std::sqrt(e);
+}
+// Polar factor of A via Newton iteration X <- (X + X^-dag)/2 with scaling (Higham); FP64.
+bool inv4(const cd* a, cd* out) {
+  cd m[4][8];
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 8; ++j) m[i][j] = j < 4 ? a[4 * i + j] : (j - 4 == i ? 1.0 : 0.0);
+  for (int c = 0; c < 4; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < 4; ++r) if (std::abs(m[r][c]) > std::abs(m[piv][c])) piv = r;
+    if (std::abs(m[piv][c]) < 1e-300) return false;
+    if (piv != c) for (int j = 0; j < 8; ++j) std::swap(m[c][j], m[piv][j]);
+    cd d = m[c][c];
+    for (int j = 0; j < 8; ++j) m[c][j] /= d;
+    for (int r = 0; r < 4; ++r)
+      if (r != c) {
+        cd f = m[r][c];
+        for (int j = 0; j < 8; ++j) m[r][j] -= f * m[c][j];
+      }
+  }
+  for (int i = 0; i < 4; ++i) for (int j = 0; j < 4; ++j) out[4 * i + j] = m[i][j + 4];
+  return true;
+}
+double fro4(const cd* a) { double s = 0; for (int i = 0; i < 16; ++i) s += std::norm(a[i]); return std::sqrt(s); }
+bool polar4(const cd* A, cd* U) {
+  M4 X, Xi, Xid;
+  for (int i = 0; i < 16; ++i) X[i] = A[i];
+  for (int it = 0; it < 100; ++it) {
+    if (!inv4(X, Xi)) return false;
+    dag4(Xi, Xid);
+    double g = std::sqrt(fro4(Xi) / fro4(X));   // Frobenius scaling
+    M4 Y;
+    double diff = 0;
+    for (int i = 0; i < 16; ++i) {
+      Y[i] = 0.5 * (g * X[i] + Xid[i] / g);
+      diff += std::norm(Y[i] - X[i]);
+    }
+    for (int i = 0; i < 16; ++i) X[i] = Y[i];
+    if (it > 2 && std::sqrt(diff) < 1e-15) break;
+  }
+  // two unscaled steps to settle at full accuracy
+  for (int it = 0; it < 2; ++it) {
+    if (!inv4(X, Xi)) return false;
+    dag4(Xi, Xid);
+    for (int i = 0; i < 16; ++i) X[i] = 0.5 * (X[i] + Xid[i]);
+  }
+  for (int i = 0; i < 16; ++i) U[i] = X[i];
+  return true;
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------------------------
+struct qhvp_ctx {
+  int device;
+};
+
+struct qhvp_problem {
+  qhvp_ctx* ctx;
+  int n, L, L_ref, Ns, K, Kr;
+  qhvp_precision prec;
+  int ckpt_every, tangent;
+  hipStream_t stream;
+  std::vector<qhvp::PassDesc> passes, ref_passes;
+  std::vector<std::pair<int, int>> seg;
+  Layout lay;
+  char* ws;
+  bool owns_ws;
+  // host staging (pinned)
+  void* h_gates;   // K*16 amplitudes (device precision)
+  void* h_dirs;
+  double* h_tov;   // Ns*4
+  double* h_env;   // K*64
+  std::vector<double> last_T, last_Om;
+  hipEvent_t ev0, ev1;
+  double last_ms;
+
+  char* phi0() { return ws + lay.off_phi0; }
+  char* slot(int i) { return ws + lay.off_slots + (size_t)i * lay.slot_bytes; }
+  char* small(size_t o) { return ws + lay.off_small + o; }
+  // slot indices: [0, n_ckpt) checkpoints of segments 1..J-1; [n_ckpt, n_ckpt+n_seg) in-segment
+  // boundaries 1..maxlen-1; last: working / backward (a, b)
+  char* ckpt(int segment) { return slot(segment - 1); }
+  char* segbuf(int i) { return slot(lay.n_ckpt + i - 1); }
+  char* work() { return slot(lay.n_ckpt + lay.n_seg); }
+  char* second(char* slotp) { return slotp + lay.state_bytes; }
+  qhvp::Prec dprec() const { return prec == QHVP_C64_ACC64 ? qhvp::P_C64 : qhvp::P_C128; }
+  size_t amp() const { return prec == QHVP_C64_ACC64 ? 8 : 16; }
+};
+
+namespace {
+
+void to_device_precision(const qhvp_problem* p, const double* src, size_t n_complex, void* dst) {
+  if (p->prec == QHVP_C64_ACC64) {
+    float* d = (float*)dst;
+    for (size_t i = 0; i < 2 * n_complex; ++i) d[i] = (float)src[i];
+  } else {
+    std::memcpy(dst, src, 2 * n_complex * sizeof(double));
+  }
+}
+
+// Forward sweep of `passes` (gates at device pointer `gates`).  mode: 0 = labels (write result to
+// phi0), 1 = ansatz sweep storing checkpoints for a later backward sweep, 2 = ansatz cost only.
+qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& passes, const void* gates,
+                          const void* dirs, int tangent, int mode) {
+  const int np = (int)passes.size();
+  const char* samples = p->small(p->lay.o_samples);
+  double* ovpart = (double*)p->small(p->lay.o_ovpart);
+  const size_t sb = p->lay.state_bytes;
+  (void)sb;
+  // segment lookup for mode 1
+  std::vector<int> seg_of(np, 0);
+  for (size_t j = 0; j < p->seg.size(); ++j)
+    for (int q = p->seg[j].first; q < p->seg[j].second; ++q) seg_of[q] = (int)j;
+  const int J = (int)p->seg.size();
+  for (int q = 0; q < np; ++q) {
+    qhvp::FwdArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.pd = passes[q];
+    a.n_samples = p->Ns;
+    a.tangent = tangent;
+    a.gates = gates;
+    a.dirs = dirs;
+    a.samples = samples;
+    char* src = nullptr;
+    char* dst = nullptr;
+    if (mode == 0) {
+      src = q == 0 ? nullptr : p->phi0();
+      dst = p->phi0();
+    } else if (mode == 2) {
+      src = q == 0 ? nullptr : p->work();
+      dst = q == np - 1 ? nullptr : p->work();
+    } else {
+      const int j = seg_of[q];
+      const int s0 = p->seg[j].first, s1 = p->seg[j].second;
+      const bool last_seg = (j == J - 1);
+      if (q == s0) src = (j == 0) ? nullptr : p->ckpt(j);
+      else src = last_seg ? p->segbuf(q - s0) : p->work();
+      if (q == np - 1) dst = nullptr;
+      else if (q + 1 == s1) dst = p->ckpt(j + 1);
+      else dst = last_seg ? p->segbuf(q + 1 - s0) : p->work();
+    }
+    a.src_psi = src;
+    a.src_dpsi = src ? p->second(src) : nullptr;
+    if (mode != 0 && q == np - 1) {
+      a.dst_psi = nullptr;
+      a.dst_dpsi = nullptr;
+      a.phi0 = p->phi0();
+      a.ov_part = ovpart;
+    } else {
+      a.dst_psi = dst;
+      a.dst_dpsi = p->second(dst);
+    }
+    LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
+  }
+  if (mode != 0) {
+    const int tiles = 1 << (p->n - passes[np - 1].mb);
+    LAUNCH_TRY(qhvp::launch_reduce_overlaps(ovpart, p->Ns, tiles, (double*)p->small(p->lay.o_tov), p->stream));
+  }
+  return QHVP_OK;
+}
+
+qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
+  const int np = (int)p->passes.size();
+  const int J = (int)p->seg.size();
+  const void* gates = p->small(p->lay.o_gates);
+  const void* dirs = p->small(p->lay.o_dirs);
+  const char* samples = p->small(p->lay.o_samples);
+  double* envpart = (double*)p->small(p->lay.o_envpart);
+  double* env = (double*)p->small(p->lay.o_env);
+  char* ab = p->work();
+  for (int j = J - 1; j >= 0; --j) {
+    const int s0 = p->seg[j].first, s1 = p->seg[j].second;
+    char* start = j == 0 ? nullptr : p->ckpt(j);
+    if (j < J - 1) {
+      // recompute the segment's inner boundaries from its checkpoint
+      for (int q = s0; q + 1 < s1; ++q) {
+        qhvp::FwdArgs a;
+        std::memset(&a, 0, sizeof(a));
+        a.pd = p->passes[q];
+        a.n_samples = p->Ns;
+        a.tangent = tangent;
+        a.gates = gates;
+        a.dirs = dirs;
+        a.samples = samples;
+        char* src = q == s0 ? start : p->segbuf(q - s0);
+        char* dst = p->segbuf(q + 1 - s0);
+        a.src_psi = src;
+        a.src_dpsi = src ? p->second(src) : nullptr;
+        a.dst_psi = dst;
+        a.dst_dpsi = p->second(dst);
+        LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
+      }
+    }
+    for (int q = s1 - 1; q >= s0; --q) {
+      qhvp::BwdArgs b;
+      std::memset(&b, 0, sizeof(b));
+      b.pd = p->passes[q];
+      b.n_samples = p->Ns;
+      b.tangent = tangent;
+      b.gates = gates;
+      b.dirs = dirs;
+      char* src = q == s0 ? start : p->segbuf(q - s0);
+      b.src_psi = src;
+      b.src_dpsi = src ? p->second(src) : nullptr;
+      b.samples = samples;
+      b.ab_a = ab;
+      b.ab_b = p->second(ab);
+      b.phi0 = p->phi0();
+      b.tov = (const double*)p->small(p->lay.o_tov);
+      b.fold = (q == np - 1);
+      b.store_ab = (q > 0);
+      b.env_part = envpart;
+      LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), b, p->stream));
+      const int nwg = qhvp::grid_size((long long)p->Ns << (p->n - b.pd.mb));
+      LAUNCH_TRY(qhvp::launch_reduce_env(envpart, nwg, b.pd, env, p->stream));
+    }
+  }
+  return QHVP_OK;
+}
+
+qhvp_status check_gates(const qhvp_problem* p, const double* G, const char* what) {
+  if (!G) return fail(QHVP_ERR_INVALID, std::string(what) + " is NULL");
+  if (!finite_all(G, (size_t)p->K * 32)) return fail(QHVP_ERR_INVALID, std::string(what) + " has non-finite entries");
+  return QHVP_OK;
+}
+
+qhvp_status run(qhvp_problem* p, const double* G, const double* V, int mode /*0 cost,1 grad,2 hvp*/) {
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  to_device_precision(p, G, (size_t)p->K * 16, p->h_gates);
+  HIP_TRY(hipEventRecord(p->ev0, p->stream));
+  HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_gates), p->h_gates, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
+  if (mode == 2) {
+    to_device_precision(p, V, (size_t)p->K * 16, p->h_dirs);
+    HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_dirs), p->h_dirs, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
+  }
+  const int tangent = mode == 2 ? 1 : 0;
+  qhvp_status st;
+  if (mode == 0) {
+    st = forward_sweep(p, p->passes, p->small(p->lay.o_gates), nullptr, 0, 2);
+    if (st) return st;
+  } else {
+    st = forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent, 1);
+    if (st) return st;
+    st = backward_sweep(p, tangent);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(p->h_env, p->small(p->lay.o_env), (size_t)p->K * qhvp::kEnvVals * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  }
+  HIP_TRY(hipMemcpyAsync(p->h_tov, p->small(p->lay.o_tov), (size_t)p->Ns * 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipEventRecord(p->ev1, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+  p->last_ms = ms;
+  p->last_T.assign(2 * p->Ns, 0.0);
+  p->last_Om.assign(2 * p->Ns, 0.0);
+  for (int s = 0; s < p->Ns; ++s) {
+    p->last_T[2 * s] = p->h_tov[4 * s];
+    p->last_T[2 * s + 1] = p->h_tov[4 * s + 1];
+    if (mode == 2) {
+      p->last_Om[2 * s] = p->h_tov[4 * s + 2];
+      p->last_Om[2 * s + 1] = p->h_tov[4 * s + 3];
+    }
+  }
+  return QHVP_OK;
+}
+
+// Alg. 2 post-processing over samples: F = mean |T_s|^2; with the folded environments
+// Ehat_k = sum_s conj(T_s) dT_s/dG_k and Dhat_k = sum_s conj(Omega_s) dT_s/dG_k + conj(T_s) D(dT_s/dG_k)[V],
+// grad C = -(2/N_s) conj(Ehat) and H(C)[V] = -(2/N_s) conj(Dhat) (cost 1 - F differentiated).
+double fidelity_of(const qhvp_problem* p) {
+  double F = 0;
+  for (int s = 0; s < p->Ns; ++s) F += p->h_tov[4 * s] * p->h_tov[4 * s] + p->h_tov[4 * s + 1] * p->h_tov[4 * s + 1];
+  return F / p->Ns;
+}
+
+void env_to_output(const qhvp_problem* p, int which, double* out) {
+  const double f = -2.0 / p->Ns;
+  for (int k = 0; k < p->K; ++k)
+    for (int e = 0; e < 16; ++e) {
+      const double re = p->h_env[(size_t)k * 64 + which * 32 + 2 * e];
+      const double im = p->h_env[(size_t)k * 64 + which * 32 + 2 * e + 1];
+      out[(size_t)k * 32 + 2 * e] = f * re;
+      out[(size_t)k * 32 + 2 * e + 1] = -f * im;
+    }
+}
+
+}  // namespace
+
+// --------------------------------------------------------------------------------------------
+extern "C" {
+
+int qhvp_version(void) { return 100; }
+
+const char* qhvp_last_error(void) { return g_err.c_str(); }
+
+int qhvp_num_gates(int n, int L) { return num_gates(n, L); }
+
+qhvp_status qhvp_ctx_create(int device, qhvp_ctx** out) {
+  if (!out) return fail(QHVP_ERR_INVALID, "out is NULL");
+  int cnt = 0;
+  HIP_TRY(hipGetDeviceCount(&cnt));
+  if (device < 0 || device >= cnt) return fail(QHVP_ERR_INVALID, "no such HIP device");
+  HIP_TRY(hipSetDevice(device));
+  *out = new qhvp_ctx{device};
+  return QHVP_OK;
+}
+
+void qhvp_ctx_destroy(qhvp_ctx* ctx) { delete ctx; }
+
+size_t qhvp_workspace_bytes(int n, int L, int L_ref, int n_samples, qhvp_precision prec, int ckpt_every,
+                            int with_tangent) {
+  if (prec != QHVP_C128 && prec != QHVP_C64_ACC64) return 0;
+  Layout lay;
+  if (!make_layout(n, L, L_ref, n_samples, prec, ckpt_every, with_tangent ? 1 : 0, lay)) return 0;
+  return lay.total;
+}
+
+qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const double* uref_gates,
+                                const double* samples, int n_samples, qhvp_precision prec, int ckpt_every,
+                                int with_tangent, void* d_workspace, size_t ws_bytes, void* hip_stream,
+                                qhvp_problem** out) {
+  if (!ctx || !out) return fail(QHVP_ERR_INVALID, "ctx or out is NULL");
+  if (n < 2 || n > qhvp::kMaxQubits) return fail(QHVP_ERR_INVALID, "n must be in [2, 30]");
+  if (L < 1 || L_ref < 1) return fail(QHVP_ERR_INVALID, "L and L_ref must be >= 1");
+  if (n_samples < 1) return fail(QHVP_ERR_INVALID, "n_samples must be >= 1");
+  if (prec != QHVP_C128 && prec != QHVP_C64_ACC64) return fail(QHVP_ERR_INVALID, "unknown precision");
+  if (!uref_gates || !samples) return fail(QHVP_ERR_INVALID, "uref_gates or samples is NULL");
+  const int Kr = num_gates(n, L_ref);
+  if (!finite_all(uref_gates, (size_t)Kr * 32)) return fail(QHVP_ERR_INVALID, "uref_gates has non-finite entries");
+  if (!finite_all(samples, (size_t)n_samples * n * 4)) return fail(QHVP_ERR_INVALID, "samples has non-finite entries");
+  Layout lay;
+  if (!make_layout(n, L, L_ref, n_samples, prec, ckpt_every, with_tangent ? 1 : 0, lay))
+    return fail(QHVP_ERR_INVALID, "invalid problem shape");
+  if (d_workspace && ws_bytes < lay.total)
+    return fail(QHVP_ERR_NOMEM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " + std::to_string(lay.total));
+  if (d_workspace && ((uintptr_t)d_workspace % kAlign) != 0) return fail(QHVP_ERR_INVALID, "workspace must be 256-byte aligned");
+  HIP_TRY(hipSetDevice(ctx->device));
+
+  qhvp_problem* p = new qhvp_problem();
+  p->ctx = ctx;
+  p->n = n; p->L = L; p->L_ref = L_ref; p->Ns = n_samples;
+  p->K = num_gates(n, L); p->Kr = Kr;
+  p->prec = prec; p->ckpt_every = ckpt_every; p->tangent = with_tangent ? 1 : 0;
+  p->stream = (hipStream_t)hip_stream;
+  p->passes = plan_circuit(n, L, nullptr);
+  p->ref_passes = plan_circuit(n, L_ref, nullptr);
+  p->seg = plan_segments(n, L, ckpt_every);
+  p->lay = lay;
+  p->last_ms = 0;
+  p->h_gates = p->h_dirs = nullptr;
+  p->h_tov = p->h_env = nullptr;
+  p->ev0 = p->ev1 = nullptr;
+  auto cleanup_fail = [&](qhvp_status st, const std::string& msg) {
+    qhvp_problem_destroy(p);
+    return fail(st, msg);
+  };
+  if (d_workspace) {
+    p->ws = (char*)d_workspace;
+    p->owns_ws = false;
+  } else {
+    p->ws = nullptr;
+    p->owns_ws = true;
+    hipError_t e = hipMalloc((void**)&p->ws, lay.total);
+    if (e != hipSuccess) { p->ws = nullptr; return cleanup_fail(QHVP_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)); }
+  }
+  const size_t amp = p->amp();
+  const size_t stage = std::max((size_t)std::max(p->K, Kr) * 16, (size_t)n_samples * n * 2) * amp;
+  if (hipHostMalloc(&p->h_gates, stage) != hipSuccess || hipHostMalloc(&p->h_dirs, stage) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_tov, (size_t)n_samples * 4 * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_env, (size_t)p->K * qhvp::kEnvVals * sizeof(double)) != hipSuccess)
+    return cleanup_fail(QHVP_ERR_NOMEM, "pinned host allocation failed");
+  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
+    return cleanup_fail(QHVP_ERR_DEVICE, "hipEventCreate failed");
+
+  // samples and U_ref gates to the device, then labels phi0 = U_ref psi (a forward sweep of U_ref)
+  to_device_precision(p, samples, (size_t)n_samples * n * 2, p->h_gates);
+  if (hipMemcpyAsync(p->small(lay.o_samples), p->h_gates, (size_t)n_samples * n * 2 * amp, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess)
+    return cleanup_fail(QHVP_ERR_DEVICE, "copy of samples failed");
+  to_device_precision(p, uref_gates, (size_t)Kr * 16, p->h_gates);
+  if (hipMemcpyAsync(p->small(lay.o_uref), p->h_gates, (size_t)Kr * 16 * amp, hipMemcpyHostToDevice, p->stream) != hipSuccess)
+    return cleanup_fail(QHVP_ERR_DEVICE, "copy of U_ref failed");
+  qhvp_status st = forward_sweep(p, p->ref_passes, p->small(lay.o_uref), nullptr, 0, 0);
+  if (st != QHVP_OK) { std::string m = g_err; qhvp_problem_destroy(p); return fail(st, m); }
+  if (hipStreamSynchronize(p->stream) != hipSuccess) return cleanup_fail(QHVP_ERR_DEVICE, "label sweep failed");
+  *out = p;
+  return QHVP_OK;
+}
+
+void qhvp_problem_destroy(qhvp_problem* p) {
+  if (!p) return;
+  if (p->stream) hipStreamSynchronize(p->stream);
+  else hipDeviceSynchronize();
+  if (p->owns_ws && p->ws) hipFree(p->ws);
+  if (p->h_gates) hipHostFree(p->h_gates);
+  if (p->h_dirs) hipHostFree(p->h_dirs);
+  if (p->h_tov) hipHostFree(p->h_tov);
+  if (p->h_env) hipHostFree(p->h_env);
+  if (p->ev0) hipEventDestroy(p->ev0);
+  if (p->ev1) hipEventDestroy(p->ev1);
+  delete p;
+}
+
+qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fidelity) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  qhvp_status st = check_gates(p, G, "G");
+  if (st) return st;
+  st = run(p, G, nullptr, 0);
+  if (st) return st;
+  const double F = fidelity_of(p);
+  if (cost) *cost = 1.0 - F;
+  if (fidelity) *fidelity = F;
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom, double* cost, double* grad) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (!grad) return fail(QHVP_ERR_INVALID, "grad is NULL");
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  qhvp_status st = check_gates(p, G, "G");
+  if (st) return st;
+  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->K, G) > 1e-10)
+    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
+  st = run(p, G, nullptr, 1);
+  if (st) return st;
+  if (cost) *cost = 1.0 - fidelity_of(p);
+  std::vector<double> g((size_t)p->K * 32);
+  env_to_output(p, 0, g.data());
+  if (geom == QHVP_RIEMANNIAN) return qhvp_project(p->K, G, g.data(), grad);
+  std::memcpy(grad, g.data(), g.size() * sizeof(double));
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
+                     double* grad, double* hvp) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (!hvp) return fail(QHVP_ERR_INVALID, "hvp is NULL");
+  if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  qhvp_status st = check_gates(p, G, "G");
+  if (st) return st;
+  st = check_gates(p, V, "V");
+  if (st) return st;
+  std::vector<double> Vt(V, V + (size_t)p->K * 32);
+  if (geom == QHVP_RIEMANNIAN) {
+    if (qhvp_unitarity_error(p->K, G) > 1e-10) return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
+    qhvp_project(p->K, G, V, Vt.data());   // the Riemannian HVP formula assumes a tangent direction
+  }
+  st = run(p, G, Vt.data(), 2);
+  if (st) return st;
+  if (cost) *cost = 1.0 - fidelity_of(p);
+  std::vector<double> g((size_t)p->K * 32), h((size_t)p->K * 32);
+  env_to_output(p, 0, g.data());
+  env_to_output(p, 1, h.data());
+  if (geom == QHVP_RIEMANNIAN) {
+    if (grad) qhvp_project(p->K, G, g.data(), grad);
+    return qhvp_riemannian_hvp(p->K, G, g.data(), h.data(), Vt.data(), hvp);
+  }
+  if (grad) std::memcpy(grad, g.data(), g.size() * sizeof(double));
+  std::memcpy(hvp, h.data(), h.size() * sizeof(double));
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (p->last_T.empty()) return fail(QHVP_ERR_INVALID, "no evaluation yet");
+  if (T) std::memcpy(T, p->last_T.data(), p->last_T.size() * sizeof(double));
+  if (Omega) std::memcpy(Omega, p->last_Om.data(), p->last_Om.size() * sizeof(double));
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size_t* ws_bytes, int* segments) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (K) *K = p->K;
+  if (n_passes) *n_passes = (int)p->passes.size();
+  if (ws_bytes) *ws_bytes = p->lay.total;
+  if (segments) *segments = (int)p->seg.size();
+  return QHVP_OK;
+}
+
+double qhvp_last_device_ms(const qhvp_problem* p) { return p ? p->last_ms : 0.0; }
+
+qhvp_status qhvp_project(int K, const double* G, const double* X, double* out) {
+  if (K < 1 || !G || !X || !out) return fail(QHVP_ERR_INVALID, "bad arguments");
+  for (int k = 0; k < K; ++k) {
+    M4 g, x, o;
+    load4(G + 32 * (size_t)k, g);
+    load4(X + 32 * (size_t)k, x);
+    project4(g, x, o);
+    store4(o, out + 32 * (size_t)k);
+  }
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_riemannian_hvp(int K, const double* G, const double* grad, const double* hvp, const double* V,
+                                double* out) {
+  if (K < 1 || !G || !grad || !hvp || !V || !out) return fail(QHVP_ERR_INVALID, "bad arguments");
+  for (int k = 0; k < K; ++k) {
+    M4 g, gr, h, v, o;
+    load4(G + 32 * (size_t)k, g);
+    load4(grad + 32 * (size_t)k, gr);
+    load4(hvp + 32 * (size_t)k, h);
+    load4(V + 32 * (size_t)k, v);
+    riem_hvp4(g, gr, h, v, o);
+    store4(o, out + 32 * (size_t)k);
+  }
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_retract(int K, const double* G, const double* xi, double* out) {
+  if (K < 1 || !G || !xi || !out) return fail(QHVP_ERR_INVALID, "bad arguments");
+  for (int k = 0; k < K; ++k) {
+    M4 g, x, a, u;
+    load4(G + 32 * (size_t)k, g);
+    load4(xi + 32 * (size_t)k, x);
+    for (int i = 0; i < 16; ++i) a[i] = g[i] + x[i];
+    if (!polar4(a, u)) return fail(QHVP_ERR_INVALID, "G + xi is singular");
+    store4(u, out + 32 * (size_t)k);
+  }
+  return QHVP_OK;
+}
+
+double qhvp_unitarity_error(int K, const double* G) {
+  if (K < 1 || !G) return INFINITY;
+  double e = 0;
+  for (int k = 0; k < K; ++k) {
+    M4 g;
+    load4(G + 32 * (size_t)k, g);
+    e = std::max(e, unitarity_err4(g));
+  }
+  return e;
+}
+
+}  // extern "C"

@@ -1,0 +1,79 @@
+// Internal declarations shared by the host runtime (qhvp_host.cpp) and the
+// gfx950 kernels (qhvp_kernels.hip).
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace qhvp {
+
+// A pass applies up to kMaxGates gates of one brickwall layer to a tile of
+// 2^mb amplitudes (mb <= kMaxTileBits) of one sample.  The tile's "active"
+// bits abit[0..mb) are statevector index bits (ascending); the low kCoalesce
+// bits are always active so that global loads and stores touch contiguous
+// runs.  The remaining (inactive) bits ibit[0..n-mb) enumerate the tiles.
+constexpr int kMaxGates = 5;
+constexpr int kMaxTileBits = 10;
+constexpr int kMaxQubits = 30;
+constexpr int kThreads = 256;     // 4 wave64s; one 4-amplitude group per thread per gate at mb = 10
+constexpr int kEnvVals = 64;      // 16 complex E + 16 complex D per gate, as 64 doubles
+
+struct PassDesc {
+  int n;      // qubits
+  int mb;     // tile bits
+  int ng;     // gates in this pass
+  int gidx[kMaxGates];          // global gate index of each gate, in application order
+  int tlo[kMaxGates];           // tile bit of qubit q+1 (less significant bit of the pair)
+  int thi[kMaxGates];           // tile bit of qubit q   (more significant bit of the pair)
+  int abit[kMaxTileBits];       // statevector bit of each tile bit
+  int ibit[kMaxQubits];         // statevector bits that index tiles, ascending
+};
+
+enum Prec { P_C128 = 0, P_C64 = 1 };
+
+// Forward pass: states (psi, dpsi) -> W psi (Eq. fis / Eq. dfis).  src_psi == nullptr means
+// "generate the product state psi^[0] from `samples`, with dpsi = 0".  If ov_part != nullptr the
+// result is not stored; instead per-tile partial overlaps with phi0 are written:
+// ov_part[s*tiles + w] = (sum conj(phi0) psi, sum conj(phi0) dpsi) as 4 doubles.
+struct FwdArgs {
+  PassDesc pd;
+  int n_samples;
+  int tangent;
+  const void* gates;   // K*16 complex (precision of the pass)
+  const void* dirs;    // K*16 complex or null
+  const void* src_psi; const void* src_dpsi;
+  const void* samples; // N_s * n * 2 complex
+  void* dst_psi; void* dst_dpsi;
+  const void* phi0;
+  double* ov_part;
+};
+
+// Backward pass over the same tile structure: (a, b) at the pass output -> at the pass input
+// (Eq. bis / Eq. dbis with the folded boundary a = T phi, b = Omega phi), accumulating the
+// per-gate environment sums.  env_part[wg][j][0..64) (doubles) receives, for gate slot j,
+// sum conj(a) psi^T (16 complex) and sum conj(b) psi^T + conj(a) dpsi^T (16 complex).
+struct BwdArgs {
+  PassDesc pd;
+  int n_samples;
+  int tangent;
+  const void* gates; const void* dirs;
+  const void* src_psi; const void* src_dpsi;  // pass-input forward states (null -> generated)
+  const void* samples;
+  void* ab_a; void* ab_b;                     // in/out backward states (in place)
+  const void* phi0; const double* tov;        // fold: a = T_s phi0, b = Omega_s phi0 when fold != 0
+  int fold;
+  int store_ab;
+  double* env_part;
+};
+
+int grid_size(long long items);
+
+// Launchers (return a hipError_t as int).
+int launch_fwd(Prec prec, const FwdArgs& a, void* stream);
+int launch_bwd(Prec prec, const BwdArgs& a, void* stream);
+// tov[s] = (T_s, Omega_s) = sum over tiles of ov_part.
+int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream);
+// env[gidx[j]][0..64) = sum over wg of env_part[wg][j][0..64), for j < ng.
+int launch_reduce_env(const double* env_part, int n_wg, const PassDesc& pd, double* env, void* stream);
+
+}  // namespace qhvp

@@ -1,0 +1,603 @@
+// gfx950 kernels for sample-batched recursive state propagation on brickwall
+// circuits (arXiv 2604.20384, Sec. II.C-F and Sec. III; Alg. 1 restructured
+// into tiled passes).
+//
+// Data layout: a state set is N_s contiguous statevectors of 2^n complex
+// amplitudes (sample-major).  A pass loads, for one sample at a time, a tile
+// of 2^mb amplitudes spanned by the pass's active index bits into LDS,
+// applies its gates (all from one layer, so they act on disjoint qubit pairs
+// and commute) one after another with a workgroup barrier between gates, and
+// writes the tile back (or reduces it against phi0).  The low index bits are
+// always active, so each global access covers contiguous runs of amplitudes.
+//
+// Backward pass: the tile holds the backward states (a, b) at the pass output
+// and the forward states (psi, dpsi) at the pass input.  The forward states
+// in front of each gate are recomputed inside the tile (instead of caching
+// one state per gate, as Alg. 1 does), then the gates are undone in reverse
+// order: for gate k the environment sum conj(a) psi^T and its directional
+// derivative sum conj(b) psi^T + conj(a) dpsi^T (Eq. environment, Eq.
+// overlap-hvp) are accumulated first, then (a, b) <- (G^dag a, G^dag b + V^dag a)
+// (Eq. bis, Eq. dbis).  The accumulation is a contraction over (sample,
+// rest-of-qubits) of 16-row x 16-column real operands, done with
+// v_mfma_*_16x16x4 so that the cross-lane reduction costs nothing; complex64
+// runs accumulate one tile in FP32 and add that into FP64 registers.
+//
+// Folding: the first backward pass starts from a = T_s phi0 and
+// b = Omega_s phi0, which carries Alg. 2's per-sample weights through the
+// (linear) backward recursion, so the environment sums over samples directly
+// give -(N_s/2) conj(grad C) and -(N_s/2) conj(H(C)[V]).
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "qhvp_internal.h"
+
+namespace qhvp {
+
+template <typename R> struct CT;
+template <> struct CT<float> { using T = float2; };
+template <> struct CT<double> { using T = double2; };
+
+template <typename R> struct Mfma;
+template <> struct Mfma<float> {
+  typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+};
+template <> struct Mfma<double> {
+  typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+};
+
+template <typename T> __device__ __forceinline__ T cz() { T r; r.x = 0; r.y = 0; return r; }
+
+// acc + a*b
+template <typename T> __device__ __forceinline__ T cfma(T a, T b, T acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+  return acc;
+}
+// acc + conj(a)*b
+template <typename T> __device__ __forceinline__ T cfmac(T a, T b, T acc) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+  return acc;
+}
+template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
+  T r;
+  r.x = a.x * b.x - a.y * b.y;
+  r.y = a.x * b.y + a.y * b.x;
+  return r;
+}
+
+// insert a zero bit at position b
+__device__ __forceinline__ int ins0(int v, int b) { return ((v >> b) << (b + 1)) | (v & ((1 << b) - 1)); }
+
+// Scatter the low `cnt` bits of v to the statevector bit positions pos[0..cnt).
+__device__ __forceinline__ long long deposit(long long v, const int* pos, int cnt) {
+  long long x = 0;
+  for (int i = 0; i < cnt; ++i) x |= ((v >> i) & 1LL) << pos[i];
+  return x;
+}
+
+// Product state amplitude at statevector index x: prod_q u_q[bit of qubit q] (Sec. IV, Haar product states).
+template <typename T>
+__device__ __forceinline__ T product_amp(const T* u, int n, long long x) {
+  T v = cz<T>();
+  v.x = 1;
+  for (int q = 0; q < n; ++q) {
+    int bit = (int)((x >> (n - 1 - q)) & 1);
+    v = cmul(v, u[2 * q + bit]);
+  }
+  return v;
+}
+
+// --------------------------------------------------------------------------------------------
+// Forward pass
+// --------------------------------------------------------------------------------------------
+template <typename R, bool TANG>
+__global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
+  using T = typename CT<R>::T;
+  constexpr int TSMAX = 1 << kMaxTileBits;
+  __shared__ T sP[TSMAX];
+  __shared__ T sD[TANG ? TSMAX : 1];
+  __shared__ T sU[2 * kMaxQubits];
+  __shared__ double sRed[kThreads / 64][4];
+  __shared__ T sG[kMaxGates * 16];
+  __shared__ T sV[TANG ? kMaxGates * 16 : 1];
+
+  const PassDesc& pd = a.pd;
+  const int tid = threadIdx.x;
+  const int n = pd.n, mb = pd.mb, ng = pd.ng;
+  const int TS = 1 << mb, ngroups = TS >> 2;
+  const long long dim = 1LL << n;
+  const int tiles = 1 << (n - mb);
+  const long long items = (long long)a.n_samples * tiles;
+  const T* __restrict__ G = (const T*)a.gates;
+  const T* __restrict__ V = (const T*)a.dirs;
+  const T* srcP = (const T*)a.src_psi;
+  const T* srcD = (const T*)a.src_dpsi;
+  T* dstP = (T*)a.dst_psi;
+  T* dstD = (T*)a.dst_dpsi;
+  const T* __restrict__ phi0 = (const T*)a.phi0;
+  const T* __restrict__ samp = (const T*)a.samples;
+  const bool gen = (srcP == nullptr);
+  const bool ovl = (a.ov_part != nullptr);
+
+  long long xa[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) xa[j] = deposit(tid + j * kThreads, pd.abit, mb);
+
+  // the pass's gates (and directions) in LDS; read there at every use, inside the tile loop
+  if (tid < ng * 16) {
+    sG[tid] = G[16 * pd.gidx[tid >> 4] + (tid & 15)];
+    if (TANG) sV[tid] = V[16 * pd.gidx[tid >> 4] + (tid & 15)];
+  }
+  __syncthreads();
+
+  const long long it0 = items * blockIdx.x / gridDim.x;
+  const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
+
+  for (long long it = it0; it < it1; ++it) {
+    const int s = (int)(it / tiles);
+    const int w = (int)(it - (long long)s * tiles);
+    const long long base = (long long)s * dim + deposit(w, pd.ibit, n - mb);
+    if (gen) {
+      if (tid < 2 * n) sU[tid] = samp[(long long)s * 2 * n + tid];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          sP[t] = product_amp(sU, n, base - (long long)s * dim + xa[j]);
+          if (TANG) sD[t] = cz<T>();
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          sP[t] = srcP[base + xa[j]];
+          if (TANG) sD[t] = srcD[base + xa[j]];
+        }
+      }
+    }
+    __syncthreads();
+
+    for (int j = 0; j < ng; ++j) {
+      const int lo = pd.tlo[j], hi = pd.thi[j];
+      const T* Gk = sG + 16 * j;
+      const T* Vk = sV + 16 * j;
+      if (tid < ngroups) {
+        const int t0 = ins0(ins0(tid, lo), hi);
+        int ix[4];
+        ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+        T p[4], d[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { p[i] = sP[ix[i]]; if (TANG) d[i] = sD[ix[i]]; }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          T np = cz<T>(), nd = cz<T>();
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const T g = Gk[4 * i + m];
+            np = cfma(g, p[m], np);
+            if (TANG) { nd = cfma(g, d[m], nd); nd = cfma(Vk[4 * i + m], p[m], nd); }
+          }
+          sP[ix[i]] = np;
+          if (TANG) sD[ix[i]] = nd;
+        }
+      }
+      __syncthreads();
+    }
+
+    if (ovl) {
+      double tr = 0, ti = 0, orr = 0, oi = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          const T ph = phi0[base + xa[j]];
+          const T ps = sP[t];
+          tr += (double)ph.x * ps.x + (double)ph.y * ps.y;
+          ti += (double)ph.x * ps.y - (double)ph.y * ps.x;
+          if (TANG) {
+            const T dp = sD[t];
+            orr += (double)ph.x * dp.x + (double)ph.y * dp.y;
+            oi += (double)ph.x * dp.y - (double)ph.y * dp.x;
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        tr += __shfl_xor(tr, off);
+        ti += __shfl_xor(ti, off);
+        orr += __shfl_xor(orr, off);
+        oi += __shfl_xor(oi, off);
+      }
+      if ((tid & 63) == 0) {
+        sRed[tid >> 6][0] = tr; sRed[tid >> 6][1] = ti; sRed[tid >> 6][2] = orr; sRed[tid >> 6][3] = oi;
+      }
+      __syncthreads();
+      if (tid < 4) {
+        double v = 0;
+        for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[wv][tid];
+        a.ov_part[it * 4 + tid] = v;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          dstP[base + xa[j]] = sP[t];
+          if (TANG) dstD[base + xa[j]] = sD[t];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------------------------
+// Backward pass with environment accumulation
+// --------------------------------------------------------------------------------------------
+
+// Position, after inserting zero bits at tile bits lo < hi, of group-index bit i.
+__device__ __forceinline__ int grp_bit_pos(int i, int lo, int hi) {
+  int p = i + (i >= lo ? 1 : 0);
+  return p + (p >= hi ? 1 : 0);
+}
+
+template <typename R, bool TANG>
+__global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
+  using T = typename CT<R>::T;
+  using M = Mfma<R>;
+  using acc_t = typename M::acc_t;
+  constexpr int TSMAX = 1 << kMaxTileBits;
+  constexpr int NST = TANG ? 2 : 1;
+  // sX: forward states (psi | dpsi), sY: backward states (a | b); element t of state st at [st*TSMAX + t]
+  __shared__ T sX[NST * TSMAX];
+  __shared__ T sY[NST * TSMAX];
+  __shared__ T sU[2 * kMaxQubits];
+  __shared__ double sM[16 * 16];
+  __shared__ T sG[kMaxGates * 16];
+  __shared__ T sV[TANG ? kMaxGates * 16 : 1];
+
+  const PassDesc& pd = a.pd;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int n = pd.n, mb = pd.mb, ng = pd.ng;
+  const int TS = 1 << mb, ngroups = TS >> 2;
+  const long long dim = 1LL << n;
+  const int tiles = 1 << (n - mb);
+  const long long items = (long long)a.n_samples * tiles;
+  const T* __restrict__ G = (const T*)a.gates;
+  const T* __restrict__ V = (const T*)a.dirs;
+  const T* srcP = (const T*)a.src_psi;
+  const T* srcD = (const T*)a.src_dpsi;
+  T* abA = (T*)a.ab_a;
+  T* abB = (T*)a.ab_b;
+  const T* __restrict__ phi0 = (const T*)a.phi0;
+  const T* __restrict__ samp = (const T*)a.samples;
+  const bool gen = (srcP == nullptr);
+
+  int xa[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) xa[j] = (int)deposit(tid + j * kThreads, pd.abit, mb);
+
+  if (tid < ng * 16) {
+    sG[tid] = G[16 * pd.gidx[tid >> 4] + (tid & 15)];
+    if (TANG) sV[tid] = V[16 * pd.gidx[tid >> 4] + (tid & 15)];
+  }
+
+  // MFMA operand of this lane: real part cri of amplitude cidx (pair index 2*b_hi + b_lo) of state
+  // cst, for group wave*64 + 4*c + sub in chunk c (A: rows = lane%16, B: columns = lane%16).
+  const int comp = lane & 15, sub = lane >> 4;
+  const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
+  const bool lane_live = TANG || cst == 0;
+  const int g_lane = wave * 64 + sub;                 // group of chunk 0
+  const int lane_scalar_off = 2 * cst * TSMAX + cri;  // in units of R
+
+  acc_t acc[kMaxGates];
+  double accd[kMaxGates][4];
+#pragma unroll
+  for (int j = 0; j < kMaxGates; ++j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) { acc[j][r] = 0; accd[j][r] = 0; }
+  }
+  __syncthreads();
+
+  const long long it0 = items * blockIdx.x / gridDim.x;
+  const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
+
+  for (long long it = it0; it < it1; ++it) {
+    const int s = (int)(it / tiles);
+    const int w = (int)(it - (long long)s * tiles);
+    const long long sbase = (long long)s * dim;
+    const long long base = sbase + deposit(w, pd.ibit, n - mb);
+
+    // ---- backward states (a, b) at the pass output
+    if (a.fold) {
+      T Ts, Os;
+      Ts.x = (R)a.tov[4 * s + 0]; Ts.y = (R)a.tov[4 * s + 1];
+      Os.x = (R)a.tov[4 * s + 2]; Os.y = (R)a.tov[4 * s + 3];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          const T ph = phi0[base + xa[j]];
+          sY[t] = cmul(Ts, ph);
+          if (TANG) sY[TSMAX + t] = cmul(Os, ph);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          sY[t] = abA[base + xa[j]];
+          if (TANG) sY[TSMAX + t] = abB[base + xa[j]];
+        }
+      }
+    }
+    // ---- forward states (psi, dpsi) at the pass input
+    if (gen) {
+      if (tid < 2 * n) sU[tid] = samp[(long long)s * 2 * n + tid];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          sX[t] = product_amp(sU, n, base - sbase + xa[j]);
+          if (TANG) sX[TSMAX + t] = cz<T>();
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          sX[t] = srcP[base + xa[j]];
+          if (TANG) sX[TSMAX + t] = srcD[base + xa[j]];
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- forward recompute inside the tile; keep this lane's MFMA B operands of every gate
+    R bop[kMaxGates][16];
+#pragma unroll
+    for (int j = 0; j < kMaxGates; ++j) {
+      if (j < ng) {
+        const int lo = pd.tlo[j], hi = pd.thi[j];
+        // element offset of chunk c = sum over the 4 bits of 4c of their inserted positions (uniform)
+        const int p0 = 1 << grp_bit_pos(2, lo, hi), p1 = 1 << grp_bit_pos(3, lo, hi);
+        const int p2 = 1 << grp_bit_pos(4, lo, hi), p3 = 1 << grp_bit_pos(5, lo, hi);
+        const int tl = ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi);
+        const R* xs = (const R*)sX + lane_scalar_off + 2 * tl;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
+          R v = 0;
+          if (lane_live && g_lane + 4 * c < ngroups) v = xs[2 * uo];
+          bop[j][c] = v;
+        }
+        if (j + 1 < ng) {
+          const T* Gk = sG + 16 * j;
+          const T* Vk = sV + 16 * j;
+          if (tid < ngroups) {
+            const int t0 = ins0(ins0(tid, lo), hi);
+            int ix[4];
+            ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+            T p[4], d[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSMAX + ix[i]]; }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              T np = cz<T>(), nd = cz<T>();
+#pragma unroll
+              for (int m = 0; m < 4; ++m) {
+                const T g = Gk[4 * i + m];
+                np = cfma(g, p[m], np);
+                if (TANG) { nd = cfma(g, d[m], nd); nd = cfma(Vk[4 * i + m], p[m], nd); }
+              }
+              sX[ix[i]] = np;
+              if (TANG) sX[TSMAX + ix[i]] = nd;
+            }
+          }
+          __syncthreads();
+        }
+      }
+    }
+
+    // ---- backward through the pass: accumulate environments, then undo the gate
+#pragma unroll
+    for (int j = kMaxGates - 1; j >= 0; --j) {
+      if (j < ng) {
+        const int lo = pd.tlo[j], hi = pd.thi[j];
+        const int p0 = 1 << grp_bit_pos(2, lo, hi), p1 = 1 << grp_bit_pos(3, lo, hi);
+        const int p2 = 1 << grp_bit_pos(4, lo, hi), p3 = 1 << grp_bit_pos(5, lo, hi);
+        const int tl = ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi);
+        const R* ys = (const R*)sY + lane_scalar_off + 2 * tl;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
+          R v = 0;
+          if (lane_live && g_lane + 4 * c < ngroups) v = ys[2 * uo];
+          acc[j] = M::step(v, bop[j][c], acc[j]);
+        }
+        const T* Gk = sG + 16 * j;
+        const T* Vk = sV + 16 * j;
+        if (tid < ngroups) {
+          const int t0 = ins0(ins0(tid, lo), hi);
+          int ix[4];
+          ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+          T pa[4], pb[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSMAX + ix[i]]; }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            T na = cz<T>(), nb = cz<T>();
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+              const T g = Gk[4 * m + i];      // (G^dag)_{im} = conj(G_{mi})
+              na = cfmac(g, pa[m], na);
+              if (TANG) { nb = cfmac(g, pb[m], nb); nb = cfmac(Vk[4 * m + i], pa[m], nb); }
+            }
+            sY[ix[i]] = na;
+            if (TANG) sY[TSMAX + ix[i]] = nb;
+          }
+        }
+        __syncthreads();
+      }
+    }
+
+    // ---- complex64: one tile's FP32 partial sums into the FP64 accumulators
+    if constexpr (std::is_same<R, float>::value) {
+#pragma unroll
+      for (int j = 0; j < kMaxGates; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) { accd[j][r] += (double)acc[j][r]; acc[j][r] = 0; }
+      }
+    }
+
+    if (a.store_ab) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int t = tid + j * kThreads;
+        if (t < TS) {
+          abA[base + xa[j]] = sY[t];
+          if (TANG) abB[base + xa[j]] = sY[TSMAX + t];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if constexpr (std::is_same<R, double>::value) {
+#pragma unroll
+    for (int j = 0; j < kMaxGates; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accd[j][r] = acc[j][r];
+    }
+  }
+
+  // ---- per-workgroup environment partials: sum the 4 waves' 16x16 blocks, then combine
+  double* sRed = (double*)sY;   // kThreads * 4 doubles fit in sY for both precisions
+#pragma unroll
+  for (int j = 0; j < kMaxGates; ++j) {
+    if (j < ng) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sRed[(wave * 64 + lane) * 4 + r] = accd[j][r];
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double v = 0;
+          for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[(wv * 64 + lane) * 4 + r];
+          sM[(4 * sub + r) * 16 + comp] = v;    // row 4*(lane/16)+r, column lane%16
+        }
+      }
+      __syncthreads();
+      if (tid < kEnvVals) {
+        const int which = tid >> 5, e = (tid >> 1) & 15, part = tid & 1;
+        const int x = e >> 2, y = e & 3;
+        // row of A component (st: 0 a, 1 b; ri: 0 re, 1 im; amplitude k), column of B (0 psi, 1 dpsi)
+#define RI(st, ri, k) (8 * (st) + 4 * (ri) + (k))
+#define P(r, c) sM[(r) * 16 + (c)]
+        double v;
+        if (which == 0) {
+          v = part == 0 ? P(RI(0, 0, x), RI(0, 0, y)) + P(RI(0, 1, x), RI(0, 1, y))
+                        : P(RI(0, 0, x), RI(0, 1, y)) - P(RI(0, 1, x), RI(0, 0, y));
+        } else {
+          v = part == 0 ? P(RI(1, 0, x), RI(0, 0, y)) + P(RI(1, 1, x), RI(0, 1, y)) +
+                              P(RI(0, 0, x), RI(1, 0, y)) + P(RI(0, 1, x), RI(1, 1, y))
+                        : P(RI(1, 0, x), RI(0, 1, y)) - P(RI(1, 1, x), RI(0, 0, y)) +
+                              P(RI(0, 0, x), RI(1, 1, y)) - P(RI(0, 1, x), RI(1, 0, y));
+        }
+#undef P
+#undef RI
+        a.env_part[((long long)blockIdx.x * kMaxGates + j) * kEnvVals + tid] = v;
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// --------------------------------------------------------------------------------------------
+// Deterministic fixed-order reductions
+// --------------------------------------------------------------------------------------------
+__global__ void k_reduce_overlaps(const double* __restrict__ ov_part, int n_samples, int tiles,
+                                  double* __restrict__ tov) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n_samples * 4) return;
+  const int s = idx >> 2, c = idx & 3;
+  double v = 0;
+  for (int w = 0; w < tiles; ++w) v += ov_part[((long long)s * tiles + w) * 4 + c];
+  tov[idx] = v;
+}
+
+__global__ void k_reduce_env(const double* __restrict__ env_part, int n_wg, PassDesc pd,
+                             double* __restrict__ env) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= pd.ng * kEnvVals) return;
+  const int j = idx / kEnvVals, o = idx - j * kEnvVals;
+  double v = 0;
+  for (int wg = 0; wg < n_wg; ++wg) v += env_part[((long long)wg * kMaxGates + j) * kEnvVals + o];
+  env[(long long)pd.gidx[j] * kEnvVals + o] = v;
+}
+
+// --------------------------------------------------------------------------------------------
+int grid_size(long long items) { return (int)(items < 2048 ? items : 2048); }
+
+int launch_fwd(Prec prec, const FwdArgs& a, void* stream) {
+  const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
+  dim3 grid(grid_size(items)), block(kThreads);
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == P_C64) {
+    if (a.tangent) hipLaunchKernelGGL((k_fwd<float, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_fwd<float, false>), grid, block, 0, st, a);
+  } else {
+    if (a.tangent) hipLaunchKernelGGL((k_fwd<double, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_fwd<double, false>), grid, block, 0, st, a);
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
+  const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
+  dim3 grid(grid_size(items)), block(kThreads);
+  hipStream_t st = (hipStream_t)stream;
+  if (prec == P_C64) {
+    if (a.tangent) hipLaunchKernelGGL((k_bwd<float, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_bwd<float, false>), grid, block, 0, st, a);
+  } else {
+    if (a.tangent) hipLaunchKernelGGL((k_bwd<double, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_bwd<double, false>), grid, block, 0, st, a);
+  }
+  return (int)hipGetLastError();
+}
+
+int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream) {
+  const int total = n_samples * 4;
+  hipLaunchKernelGGL(k_reduce_overlaps, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     ov_part, n_samples, tiles, tov);
+  return (int)hipGetLastError();
+}
+
+int launch_reduce_env(const double* env_part, int n_wg, const PassDesc& pd, double* env, void* stream) {
+  const int total = pd.ng * kEnvVals;
+  hipLaunchKernelGGL(k_reduce_env, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                     env_part, n_wg, pd, env);
+  return (int)hipGetLastError();
+}
+
+}  // namespace qhvp
