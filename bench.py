@@ -1,0 +1,153 @@
+"""Benchmark: Hessian-vector products per second of the brickwall Hilbert-Schmidt cost at
+n=20 qubits, L=20 layers (K=190 gates), N_s=256 Haar product samples, U_ref a Haar brickwall
+of depth 40, complex64 states with FP64 accumulation, on one MI355X.
+
+One step = one from-scratch HVP call (cost + gradient + HVP for one (G, V) over all samples);
+the labels phi_s = U_ref psi_s are computed once per problem (the problem statement takes
+them as input) and reported separately as setup time.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+VALU_PEAK_TFS = 78.6           # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 non-packed = FP64 vector)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=20)
+    ap.add_argument("--L", type=int, default=20)
+    ap.add_argument("--ns", type=int, default=256)
+    ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
+    ap.add_argument("--ckpt", type=int, default=1, help="layer checkpoint interval (0: every pass boundary)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--seed", type=int, default=1)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, L, seed):
+    """The oracle (numpy complex128 statevector Alg. 1 + 2) on one sample of the same workload."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+
+    from oracle import circuit, sv
+    from paper_2604_20384_amd.inputs import make_problem
+
+    p = make_problem(n, L, 1, seed=seed)
+    psi, phi = circuit.labels(p.uref, p.samples, n, p.L_ref)
+    t0 = time.perf_counter()
+    sv.evaluate(psi, phi, p.G, p.V, n, L, batch=1)
+    dt = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    return dt, threads
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2604_20384_amd.api import Problem, num_gates
+    from paper_2604_20384_amd.inputs import make_problem
+
+    n, L, ns = args.n, args.L, args.ns
+    K = num_gates(n, L)
+    prob = make_problem(n, L, ns, seed=args.seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gp = Problem(n, L, prob.uref, prob.samples, L_ref=prob.L_ref, precision=args.precision,
+                 ckpt_every=args.ckpt, device=0)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        gp.hvp(prob.G, prob.V)
+    gp.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        c, g, h = gp.hvp(prob.G, prob.V)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = gp.kernel_stats()
+    peak_mem = torch.cuda.max_memory_allocated()
+    hvps = args.steps / dt
+    ms_per_step = 1e3 * dt / args.steps
+
+    S = ns * 2 ** n * (8 if args.precision == "c64" else 16)
+    alg_bytes_step = sum(v["bytes"] for v in stats.values()) / args.steps
+
+    # dominant kernel: most device time over the timed region
+    dom = max(("forward", "recompute", "backward"), key=lambda k: stats[k]["ms"])
+    st = stats[dom]
+    avg_ms = st["ms"] / max(1, st["launches"])
+    bytes_per_launch = st["bytes"] / max(1, st["launches"])
+    flops_per_launch = st["flops"] / max(1, st["launches"])
+    gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    tfs = flops_per_launch / (avg_ms * 1e-3) / 1e12
+    frac_hbm, frac_alu = gbs / HBM_PEAK_GBS, tfs / VALU_PEAK_TFS
+    if frac_hbm >= frac_alu:
+        roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(frac_hbm, 4)}
+    else:
+        roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": VALU_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": round(frac_alu, 4)}
+    roof.update({"traffic": None, "kernel": f"k_bwd<{'float' if args.precision == 'c64' else 'double'},true>"
+                 if dom == "backward" else f"k_fwd<{'float' if args.precision == 'c64' else 'double'},true>",
+                 "avg_launch_ms": round(avg_ms, 4), "launches": st["launches"],
+                 "alg_bytes_per_launch": bytes_per_launch, "alg_flops_per_launch": flops_per_launch,
+                 "hbm_frac": round(frac_hbm, 4), "alu_frac": round(frac_alu, 4)})
+
+    out = {
+        "metric": "HVPs/sec (n=20, L=20, N_s=256)",
+        "value": round(hvps, 4),
+        "unit": "HVP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c64+f64acc" if args.precision == "c64" else "c128",
+        "data": "synthetic (Haar gates, Haar brickwall U_ref of depth 2L, Haar product samples, tangent V)",
+        "config": {"workload": f"brickwall HS-test HVP n={n} L={L} K={K} N_s={ns} L_ref={prob.L_ref}",
+                   "precision": args.precision, "ckpt_every_layers": args.ckpt,
+                   "passes_per_sweep": gp.info()["n_passes"]},
+        "effective_alg_GBps": round(alg_bytes_step * hvps / 1e9, 1),
+        "alg_bytes_per_hvp": alg_bytes_step,
+        "setup_s": round(setup_s, 3),
+        "peak_hbm_GiB": round(peak_mem / 2 ** 30, 2),
+        "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in stats.items()},
+        "roofline": roof,
+    }
+    gp.close()
+    del gp
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        t_sample, threads = cpu_baseline(n, L, args.seed)
+        out["cpu_baseline"] = {"value": 1.0 / (ns * t_sample), "unit": "HVP/s", "cores": threads,
+                               "kind": "oracle",
+                               "sample": f"one of the {ns} samples (n={n}, L={L}) through the numpy complex128 "
+                                         f"oracle took {t_sample:.1f} s; value = 1 / ({ns} * t), samples are independent"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

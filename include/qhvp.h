@@ -137,6 +137,25 @@ qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size
 /* Milliseconds spent on the device by the last call (HIP events around it). */
 double qhvp_last_device_ms(const qhvp_problem* p);
 
+/* ---- per-kernel timing (HIP events around every launch on the problem's stream) ---- */
+
+typedef enum {
+  QHVP_KERNEL_FORWARD = 0,    /* forward passes of the ansatz sweep (Eq. fis / Eq. dfis) */
+  QHVP_KERNEL_RECOMPUTE = 1,  /* forward passes recomputing a segment from its layer checkpoint */
+  QHVP_KERNEL_BACKWARD = 2,   /* backward passes with environment sums (Eq. bis / dbis / environment) */
+  QHVP_KERNEL_REDUCE = 3,     /* fixed-order reductions of the per-workgroup environment partials */
+  QHVP_KERNEL_KINDS = 4
+} qhvp_kernel_kind;
+
+/* Switch per-launch timing on (1) or off (0) for later calls; either way resets the statistics. */
+qhvp_status qhvp_set_profiling(qhvp_problem* p, int on);
+
+/* Accumulated statistics of one kernel kind since the last qhvp_set_profiling: total device
+ * milliseconds, number of launches, and the algorithmic HBM bytes and flops of those launches
+ * (states read and written once per pass; gate arithmetic without the in-tile recomputation). */
+qhvp_status qhvp_kernel_stats(const qhvp_problem* p, int kind, double* total_ms, long long* launches,
+                              double* alg_bytes, double* alg_flops);
+
 /* ---- FP64 host utilities on gate vectors (App. F); all arrays K*16 complex ---- */
 
 /* out = P_G(X) = X/2 - G X^dag G / 2, gate by gate (Eq. projec). */

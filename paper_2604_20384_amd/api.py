@@ -154,6 +154,20 @@ class Problem:
         check(lib.qhvp_problem_info(self.handle, C.byref(K), C.byref(npass), C.byref(ws), C.byref(seg)))
         return {"K": K.value, "n_passes": npass.value, "ws_bytes": ws.value, "segments": seg.value}
 
+    KERNEL_KINDS = ("forward", "recompute", "backward", "reduce")
+
+    def set_profiling(self, on: bool = True):
+        check(lib.qhvp_set_profiling(self.handle, int(on)))
+
+    def kernel_stats(self):
+        out = {}
+        for k, name in enumerate(self.KERNEL_KINDS):
+            ms, nb, fl = C.c_double(), C.c_double(), C.c_double()
+            cnt = C.c_longlong()
+            check(lib.qhvp_kernel_stats(self.handle, k, C.byref(ms), C.byref(cnt), C.byref(nb), C.byref(fl)))
+            out[name] = {"ms": ms.value, "launches": cnt.value, "bytes": nb.value, "flops": fl.value}
+        return out
+
     @property
     def last_device_ms(self) -> float:
         return lib.qhvp_last_device_ms(self.handle)

@@ -298,6 +298,14 @@ struct qhvp_problem {
   std::vector<double> last_T, last_Om;
   hipEvent_t ev0, ev1;
   double last_ms;
+  // optional per-launch timing: events bracket every launch of the call; stats accumulate per kind
+  int profiling = 0;
+  std::vector<hipEvent_t> evpool;
+  size_t ev_used = 0;
+  struct Pending { int kind; size_t e0; double bytes, flops; };
+  std::vector<Pending> pending;
+  double k_ms[QHVP_KERNEL_KINDS] = {0}, k_bytes[QHVP_KERNEL_KINDS] = {0}, k_flops[QHVP_KERNEL_KINDS] = {0};
+  long long k_count[QHVP_KERNEL_KINDS] = {0};
 
   char* phi0() { return ws + lay.off_phi0; }
   char* slot(int i) { return ws + lay.off_slots + (size_t)i * lay.slot_bytes; }
@@ -313,6 +321,49 @@ struct qhvp_problem {
 };
 
 namespace {
+
+// Per-launch timing (only when profiling is on): an event before and after the launch.
+hipError_t prof_begin(qhvp_problem* p) {
+  if (!p->profiling) return hipSuccess;
+  while (p->evpool.size() < p->ev_used + 2) {
+    hipEvent_t e;
+    hipError_t r = hipEventCreate(&e);
+    if (r != hipSuccess) return r;
+    p->evpool.push_back(e);
+  }
+  return hipEventRecord(p->evpool[p->ev_used], p->stream);
+}
+hipError_t prof_end(qhvp_problem* p, int kind, double bytes, double flops) {
+  if (!p->profiling) return hipSuccess;
+  hipError_t r = hipEventRecord(p->evpool[p->ev_used + 1], p->stream);
+  p->pending.push_back({kind, p->ev_used, bytes, flops});
+  p->ev_used += 2;
+  return r;
+}
+hipError_t prof_collect(qhvp_problem* p) {
+  for (auto& q : p->pending) {
+    float ms = 0;
+    hipError_t r = hipEventElapsedTime(&ms, p->evpool[q.e0], p->evpool[q.e0 + 1]);
+    if (r != hipSuccess) return r;
+    p->k_ms[q.kind] += ms;
+    p->k_bytes[q.kind] += q.bytes;
+    p->k_flops[q.kind] += q.flops;
+    p->k_count[q.kind] += 1;
+  }
+  p->pending.clear();
+  p->ev_used = 0;
+  return hipSuccess;
+}
+
+// Algorithmic traffic and arithmetic of one pass (what the method must move / compute for
+// it, not counting the in-tile recomputation): S bytes per state set read or written; per gate
+// and amplitude 32 flop for psi <- G psi, 96 with the tangent; the backward adds the environment
+// products (32 flop, 96 with the tangent).
+double state_bytes_alg(const qhvp_problem* p) { return (double)p->Ns * std::ldexp(1.0, p->n) * (double)p->amp(); }
+double pass_flops(const qhvp_problem* p, const qhvp::PassDesc& pd, int tangent, bool backward) {
+  const double per = tangent ? 96.0 : 32.0;
+  return (backward ? 2.0 : 1.0) * per * pd.ng * (double)p->Ns * std::ldexp(1.0, p->n);
+}
 
 void to_device_precision(const qhvp_problem* p, const double* src, size_t n_complex, void* dst) {
   if (p->prec == QHVP_C64_ACC64) {
@@ -375,7 +426,13 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
       a.dst_psi = dst;
       a.dst_dpsi = p->second(dst);
     }
-    LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
+    {
+      const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
+      const double bytes = (a.src_psi ? nst * S : 0) + (a.ov_part ? S : nst * S);
+      HIP_TRY(prof_begin(p));
+      LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
+      HIP_TRY(prof_end(p, QHVP_KERNEL_FORWARD, bytes, pass_flops(p, a.pd, tangent, false)));
+    }
   }
   if (mode != 0) {
     const int tiles = 1 << (p->n - passes[np - 1].mb);
@@ -413,7 +470,10 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
         a.src_dpsi = src ? p->second(src) : nullptr;
         a.dst_psi = dst;
         a.dst_dpsi = p->second(dst);
+        const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
+        HIP_TRY(prof_begin(p));
         LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
+        HIP_TRY(prof_end(p, QHVP_KERNEL_RECOMPUTE, (src ? nst * S : 0) + nst * S, pass_flops(p, a.pd, tangent, false)));
       }
     }
     for (int q = s1 - 1; q >= s0; --q) {
@@ -435,9 +495,15 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       b.fold = (q == np - 1);
       b.store_ab = (q > 0);
       b.env_part = envpart;
+      const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
+      const double bytes = (b.fold ? S : nst * S) + (src ? nst * S : 0) + (b.store_ab ? nst * S : 0);
+      HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), b, p->stream));
+      HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, bytes, pass_flops(p, b.pd, tangent, true)));
       const int nwg = qhvp::grid_size((long long)p->Ns << (p->n - b.pd.mb));
+      HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_reduce_env(envpart, nwg, b.pd, env, p->stream));
+      HIP_TRY(prof_end(p, QHVP_KERNEL_REDUCE, (double)nwg * b.pd.ng * qhvp::kEnvVals * 8, 0));
     }
   }
   return QHVP_OK;
@@ -476,6 +542,7 @@ qhvp_status run(qhvp_problem* p, const double* G, const double* V, int mode /*0 
   float ms = 0;
   HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
   p->last_ms = ms;
+  HIP_TRY(prof_collect(p));
   p->last_T.assign(2 * p->Ns, 0.0);
   p->last_Om.assign(2 * p->Ns, 0.0);
   for (int s = 0; s < p->Ns; ++s) {
@@ -623,6 +690,7 @@ void qhvp_problem_destroy(qhvp_problem* p) {
   if (p->h_env) hipHostFree(p->h_env);
   if (p->ev0) hipEventDestroy(p->ev0);
   if (p->ev1) hipEventDestroy(p->ev1);
+  for (auto e : p->evpool) hipEventDestroy(e);
   delete p;
 }
 
@@ -704,6 +772,23 @@ qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size
 }
 
 double qhvp_last_device_ms(const qhvp_problem* p) { return p ? p->last_ms : 0.0; }
+
+qhvp_status qhvp_set_profiling(qhvp_problem* p, int on) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  p->profiling = on ? 1 : 0;
+  for (int k = 0; k < QHVP_KERNEL_KINDS; ++k) { p->k_ms[k] = p->k_bytes[k] = p->k_flops[k] = 0; p->k_count[k] = 0; }
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_kernel_stats(const qhvp_problem* p, int kind, double* total_ms, long long* launches,
+                              double* alg_bytes, double* alg_flops) {
+  if (!p || kind < 0 || kind >= QHVP_KERNEL_KINDS) return fail(QHVP_ERR_INVALID, "bad arguments");
+  if (total_ms) *total_ms = p->k_ms[kind];
+  if (launches) *launches = p->k_count[kind];
+  if (alg_bytes) *alg_bytes = p->k_bytes[kind];
+  if (alg_flops) *alg_flops = p->k_flops[kind];
+  return QHVP_OK;
+}
 
 qhvp_status qhvp_project(int K, const double* G, const double* X, double* out) {
   if (K < 1 || !G || !X || !out) return fail(QHVP_ERR_INVALID, "bad arguments");

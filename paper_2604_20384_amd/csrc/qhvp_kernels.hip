@@ -39,14 +39,18 @@ template <> struct CT<float> { using T = float2; };
 template <> struct CT<double> { using T = double2; };
 
 template <typename R> struct Mfma;
+// Output row held in accumulator item r by a lane of 16-lane block `blk` (= lane / 16); the
+// column is lane % 16 for both.  A operand: lane holds A[lane % 16][lane / 16]; B: B[lane / 16][lane % 16].
 template <> struct Mfma<float> {
   typedef float acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int out_row(int blk, int r) { return 4 * blk + r; }
   static __device__ __forceinline__ acc_t step(float a, float b, acc_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
 };
 template <> struct Mfma<double> {
   typedef double acc_t __attribute__((ext_vector_type(4)));
+  static __device__ __forceinline__ int out_row(int blk, int r) { return 4 * r + blk; }
   static __device__ __forceinline__ acc_t step(double a, double b, acc_t c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
@@ -503,7 +507,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
         for (int r = 0; r < 4; ++r) {
           double v = 0;
           for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[(wv * 64 + lane) * 4 + r];
-          sM[(4 * sub + r) * 16 + comp] = v;    // row 4*(lane/16)+r, column lane%16
+          sM[M::out_row(sub, r) * 16 + comp] = v;
         }
       }
       __syncthreads();
