@@ -123,7 +123,7 @@ std::vector<std::pair<int, int>> plan_segments(int n, int L, int ckpt_every) {
   if (ckpt_every > 0) {
     for (int l = 0; l < L; l += ckpt_every) {
       int l1 = std::min(L, l + ckpt_every);
-      seg.push_back({lfp[l], lfp[l1]});
+      if (lfp[l1] > lfp[l]) seg.push_back({lfp[l], lfp[l1]});   // layers without gates (n = 2) add no segment
     }
   } else {
     int c = ckpt_every == 0 ? 1 : -ckpt_every;
