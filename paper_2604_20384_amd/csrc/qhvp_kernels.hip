@@ -81,6 +81,14 @@ template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
   return r;
 }
 
+// Uniform pointer to gate entries, made opaque to the optimiser so that the (scalar) loads of the
+// entries stay next to their use instead of being hoisted out of the tile loop into vector registers.
+template <typename T>
+__device__ __forceinline__ const T* opaque(const T* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
 // insert a zero bit at position b
 __device__ __forceinline__ int ins0(int v, int b) { return ((v >> b) << (b + 1)) | (v & ((1 << b) - 1)); }
 
@@ -114,8 +122,6 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   __shared__ T sD[TANG ? TSMAX : 1];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sRed[kThreads / 64][4];
-  __shared__ T sG[kMaxGates * 16];
-  __shared__ T sV[TANG ? kMaxGates * 16 : 1];
 
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
@@ -138,13 +144,6 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   long long xa[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) xa[j] = deposit(tid + j * kThreads, pd.abit, mb);
-
-  // the pass's gates (and directions) in LDS; read there at every use, inside the tile loop
-  if (tid < ng * 16) {
-    sG[tid] = G[16 * pd.gidx[tid >> 4] + (tid & 15)];
-    if (TANG) sV[tid] = V[16 * pd.gidx[tid >> 4] + (tid & 15)];
-  }
-  __syncthreads();
 
   const long long it0 = items * blockIdx.x / gridDim.x;
   const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
@@ -178,8 +177,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
 
     for (int j = 0; j < ng; ++j) {
       const int lo = pd.tlo[j], hi = pd.thi[j];
-      const T* Gk = sG + 16 * j;
-      const T* Vk = sV + 16 * j;
+      const T* Gk = opaque(G + 16 * pd.gidx[j]);
+      const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
       if (tid < ngroups) {
         const int t0 = ins0(ins0(tid, lo), hi);
         int ix[4];
@@ -272,8 +271,6 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   __shared__ T sY[NST * TSMAX];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sM[16 * 16];
-  __shared__ T sG[kMaxGates * 16];
-  __shared__ T sV[TANG ? kMaxGates * 16 : 1];
 
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
@@ -297,10 +294,6 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
   for (int j = 0; j < 4; ++j) xa[j] = (int)deposit(tid + j * kThreads, pd.abit, mb);
 
-  if (tid < ng * 16) {
-    sG[tid] = G[16 * pd.gidx[tid >> 4] + (tid & 15)];
-    if (TANG) sV[tid] = V[16 * pd.gidx[tid >> 4] + (tid & 15)];
-  }
 
   // MFMA operand of this lane: real part cri of amplitude cidx (pair index 2*b_hi + b_lo) of state
   // cst, for group wave*64 + 4*c + sub in chunk c (A: rows = lane%16, B: columns = lane%16).
@@ -395,8 +388,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           bop[j][c] = v;
         }
         if (j + 1 < ng) {
-          const T* Gk = sG + 16 * j;
-          const T* Vk = sV + 16 * j;
+          const T* Gk = opaque(G + 16 * pd.gidx[j]);
+          const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
           if (tid < ngroups) {
             const int t0 = ins0(ins0(tid, lo), hi);
             int ix[4];
@@ -438,8 +431,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           if (lane_live && g_lane + 4 * c < ngroups) v = ys[2 * uo];
           acc[j] = M::step(v, bop[j][c], acc[j]);
         }
-        const T* Gk = sG + 16 * j;
-        const T* Vk = sV + 16 * j;
+        const T* Gk = opaque(G + 16 * pd.gidx[j]);
+        const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
         if (tid < ngroups) {
           const int t0 = ins0(ins0(tid, lo), hi);
           int ix[4];
@@ -539,24 +532,40 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 // --------------------------------------------------------------------------------------------
 // Deterministic fixed-order reductions
 // --------------------------------------------------------------------------------------------
-__global__ void k_reduce_overlaps(const double* __restrict__ ov_part, int n_samples, int tiles,
-                                  double* __restrict__ tov) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n_samples * 4) return;
-  const int s = idx >> 2, c = idx & 3;
+// One block per sample: thread t sums tiles w = t/4, t/4 + 64, ... of component t%4, then the 64
+// partial sums are added in a fixed order.
+__global__ void __launch_bounds__(256) k_reduce_overlaps(const double* __restrict__ ov_part, int n_samples,
+                                                         int tiles, double* __restrict__ tov) {
+  __shared__ double red[64][4];
+  const int s = blockIdx.x;
+  const int c = threadIdx.x & 3, chunk = threadIdx.x >> 2;
   double v = 0;
-  for (int w = 0; w < tiles; ++w) v += ov_part[((long long)s * tiles + w) * 4 + c];
-  tov[idx] = v;
+  for (int w = chunk; w < tiles; w += 64) v += ov_part[((long long)s * tiles + w) * 4 + c];
+  red[chunk][c] = v;
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0;
+    for (int k = 0; k < 64; ++k) t += red[k][c];
+    tov[4 * s + c] = t;
+  }
 }
 
-__global__ void k_reduce_env(const double* __restrict__ env_part, int n_wg, PassDesc pd,
-                             double* __restrict__ env) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= pd.ng * kEnvVals) return;
-  const int j = idx / kEnvVals, o = idx - j * kEnvVals;
+// One block per gate slot j: thread t sums workgroups wg = t/64, t/64 + 16, ... for output t%64,
+// then the 16 partial sums are added in a fixed order.
+__global__ void __launch_bounds__(1024) k_reduce_env(const double* __restrict__ env_part, int n_wg, PassDesc pd,
+                                                     double* __restrict__ env) {
+  __shared__ double red[16][kEnvVals];
+  const int j = blockIdx.x;
+  const int o = threadIdx.x & 63, chunk = threadIdx.x >> 6;
   double v = 0;
-  for (int wg = 0; wg < n_wg; ++wg) v += env_part[((long long)wg * kMaxGates + j) * kEnvVals + o];
-  env[(long long)pd.gidx[j] * kEnvVals + o] = v;
+  for (int wg = chunk; wg < n_wg; wg += 16) v += env_part[((long long)wg * kMaxGates + j) * kEnvVals + o];
+  red[chunk][o] = v;
+  __syncthreads();
+  if (threadIdx.x < kEnvVals) {
+    double t = 0;
+    for (int c = 0; c < 16; ++c) t += red[c][o];
+    env[(long long)pd.gidx[j] * kEnvVals + o] = t;
+  }
 }
 
 // --------------------------------------------------------------------------------------------
@@ -591,16 +600,13 @@ int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
 }
 
 int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream) {
-  const int total = n_samples * 4;
-  hipLaunchKernelGGL(k_reduce_overlaps, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                     ov_part, n_samples, tiles, tov);
+  hipLaunchKernelGGL(k_reduce_overlaps, dim3(n_samples), dim3(256), 0, (hipStream_t)stream, ov_part, n_samples,
+                     tiles, tov);
   return (int)hipGetLastError();
 }
 
 int launch_reduce_env(const double* env_part, int n_wg, const PassDesc& pd, double* env, void* stream) {
-  const int total = pd.ng * kEnvVals;
-  hipLaunchKernelGGL(k_reduce_env, dim3((total + 255) / 256), dim3(256), 0, (hipStream_t)stream,
-                     env_part, n_wg, pd, env);
+  hipLaunchKernelGGL(k_reduce_env, dim3(pd.ng), dim3(1024), 0, (hipStream_t)stream, env_part, n_wg, pd, env);
   return (int)hipGetLastError();
 }
 
