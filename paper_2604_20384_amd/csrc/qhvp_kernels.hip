@@ -89,6 +89,64 @@ __device__ __forceinline__ const T* opaque(const T* p) {
   return p;
 }
 
+// (p, d) <- (G p, G d + V p) on one 4-amplitude group (Eq. fis / Eq. dfis); the V terms come after a
+// compiler barrier so that only one matrix's scalar entries are live at a time.
+template <typename T, bool TANG>
+__device__ __forceinline__ void apply_w(const T* G, const T* V, T (&p)[4], T (&d)[4]) {
+  T np[4], nd[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    np[i] = cz<T>();
+    nd[i] = cz<T>();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const T g = G[4 * i + m];
+      np[i] = cfma(g, p[m], np[i]);
+      if (TANG) nd[i] = cfma(g, d[m], nd[i]);
+    }
+  }
+  if (TANG) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) nd[i] = cfma(V[4 * i + m], p[m], nd[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { p[i] = np[i]; if (TANG) d[i] = nd[i]; }
+}
+
+// (a, b) <- (G^dag a, G^dag b + V^dag a) (Eq. bis / Eq. dbis), same phase split.
+template <typename T, bool TANG>
+__device__ __forceinline__ void apply_wdag(const T* G, const T* V, T (&a)[4], T (&b)[4]) {
+  T na[4], nb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    na[i] = cz<T>();
+    nb[i] = cz<T>();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const T g = G[4 * m + i];          // (G^dag)_{im} = conj(G_{mi})
+      na[i] = cfmac(g, a[m], na[i]);
+      if (TANG) nb[i] = cfmac(g, b[m], nb[i]);
+    }
+  }
+  if (TANG) {
+    asm volatile("" ::: "memory");
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) nb[i] = cfmac(V[4 * m + i], a[m], nb[i]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) { a[i] = na[i]; if (TANG) b[i] = nb[i]; }
+}
+
+__device__ __forceinline__ int opaque_int(int v) {
+  asm volatile("" : "+s"(v));
+  return v;
+}
+
 // insert a zero bit at position b
 __device__ __forceinline__ int ins0(int v, int b) { return ((v >> b) << (b + 1)) | (v & ((1 << b) - 1)); }
 
@@ -176,7 +234,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
     __syncthreads();
 
     for (int j = 0; j < ng; ++j) {
-      const int lo = pd.tlo[j], hi = pd.thi[j];
+      const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
       const T* Gk = opaque(G + 16 * pd.gidx[j]);
       const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
       if (tid < ngroups) {
@@ -186,18 +244,9 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         T p[4], d[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) { p[i] = sP[ix[i]]; if (TANG) d[i] = sD[ix[i]]; }
+        apply_w<T, TANG>(Gk, Vk, p, d);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          T np = cz<T>(), nd = cz<T>();
-#pragma unroll
-          for (int m = 0; m < 4; ++m) {
-            const T g = Gk[4 * i + m];
-            np = cfma(g, p[m], np);
-            if (TANG) { nd = cfma(g, d[m], nd); nd = cfma(Vk[4 * i + m], p[m], nd); }
-          }
-          sP[ix[i]] = np;
-          if (TANG) sD[ix[i]] = nd;
-        }
+        for (int i = 0; i < 4; ++i) { sP[ix[i]] = p[i]; if (TANG) sD[ix[i]] = d[i]; }
       }
       __syncthreads();
     }
@@ -299,9 +348,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   // cst, for group wave*64 + 4*c + sub in chunk c (A: rows = lane%16, B: columns = lane%16).
   const int comp = lane & 15, sub = lane >> 4;
   const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
-  const bool lane_live = TANG || cst == 0;
+  // Without tangent states the b rows / dpsi columns only feed the unused D sums; those lanes read
+  // the a / psi arrays (in bounds) and their products are discarded.
   const int g_lane = wave * 64 + sub;                 // group of chunk 0
-  const int lane_scalar_off = 2 * cst * TSMAX + cri;  // in units of R
+  const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSMAX + cri;  // in units of R
 
   acc_t acc[kMaxGates];
   double accd[kMaxGates][4];
@@ -309,6 +359,12 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   for (int j = 0; j < kMaxGates; ++j) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) { acc[j][r] = 0; accd[j][r] = 0; }
+  }
+  // Groups g >= ngroups (only when mb < kMaxTileBits) map to tile indices >= 2^mb, which no tile
+  // operation writes: zero them once so that their MFMA operands are zero.
+  for (int t = TS + tid; t < TSMAX; t += kThreads) {
+    sX[t] = cz<T>(); sY[t] = cz<T>();
+    if (TANG) { sX[TSMAX + t] = cz<T>(); sY[TSMAX + t] = cz<T>(); }
   }
   __syncthreads();
 
@@ -374,7 +430,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
     for (int j = 0; j < kMaxGates; ++j) {
       if (j < ng) {
-        const int lo = pd.tlo[j], hi = pd.thi[j];
+        const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
         // element offset of chunk c = sum over the 4 bits of 4c of their inserted positions (uniform)
         const int p0 = 1 << grp_bit_pos(2, lo, hi), p1 = 1 << grp_bit_pos(3, lo, hi);
         const int p2 = 1 << grp_bit_pos(4, lo, hi), p3 = 1 << grp_bit_pos(5, lo, hi);
@@ -383,9 +439,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
-          R v = 0;
-          if (lane_live && g_lane + 4 * c < ngroups) v = xs[2 * uo];
-          bop[j][c] = v;
+          bop[j][c] = xs[2 * uo];
         }
         if (j + 1 < ng) {
           const T* Gk = opaque(G + 16 * pd.gidx[j]);
@@ -397,18 +451,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
             T p[4], d[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSMAX + ix[i]]; }
+            apply_w<T, TANG>(Gk, Vk, p, d);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              T np = cz<T>(), nd = cz<T>();
-#pragma unroll
-              for (int m = 0; m < 4; ++m) {
-                const T g = Gk[4 * i + m];
-                np = cfma(g, p[m], np);
-                if (TANG) { nd = cfma(g, d[m], nd); nd = cfma(Vk[4 * i + m], p[m], nd); }
-              }
-              sX[ix[i]] = np;
-              if (TANG) sX[TSMAX + ix[i]] = nd;
-            }
+            for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSMAX + ix[i]] = d[i]; }
           }
           __syncthreads();
         }
@@ -419,7 +464,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
     for (int j = kMaxGates - 1; j >= 0; --j) {
       if (j < ng) {
-        const int lo = pd.tlo[j], hi = pd.thi[j];
+        const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
         const int p0 = 1 << grp_bit_pos(2, lo, hi), p1 = 1 << grp_bit_pos(3, lo, hi);
         const int p2 = 1 << grp_bit_pos(4, lo, hi), p3 = 1 << grp_bit_pos(5, lo, hi);
         const int tl = ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi);
@@ -427,9 +472,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
-          R v = 0;
-          if (lane_live && g_lane + 4 * c < ngroups) v = ys[2 * uo];
-          acc[j] = M::step(v, bop[j][c], acc[j]);
+          acc[j] = M::step(ys[2 * uo], bop[j][c], acc[j]);
         }
         const T* Gk = opaque(G + 16 * pd.gidx[j]);
         const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
@@ -440,18 +483,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           T pa[4], pb[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSMAX + ix[i]]; }
+          apply_wdag<T, TANG>(Gk, Vk, pa, pb);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            T na = cz<T>(), nb = cz<T>();
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-              const T g = Gk[4 * m + i];      // (G^dag)_{im} = conj(G_{mi})
-              na = cfmac(g, pa[m], na);
-              if (TANG) { nb = cfmac(g, pb[m], nb); nb = cfmac(Vk[4 * m + i], pa[m], nb); }
-            }
-            sY[ix[i]] = na;
-            if (TANG) sY[TSMAX + ix[i]] = nb;
-          }
+          for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSMAX + ix[i]] = pb[i]; }
         }
         __syncthreads();
       }
