@@ -147,6 +147,17 @@ __device__ __forceinline__ int opaque_int(int v) {
   return v;
 }
 
+// Padded LDS index of tile element t: one spare element after every 256-byte row, so that the
+// power-of-two strides of gates on low tile bits spread over all banks.  Additive over index
+// values with disjoint bits (used to split MFMA operand addresses into lane + uniform parts).
+template <typename T> struct Lds {
+  static constexpr int PS = sizeof(T) == 8 ? 5 : 4;                      // log2(elements per 256 B)
+  static constexpr int TSMAX = 1 << kMaxTileBits;
+  // padded size of one state array, +32 bytes so that a second state array starts 8 banks over
+  static constexpr int TSP = TSMAX + (TSMAX >> PS) + 32 / (int)sizeof(T);
+  static __device__ __forceinline__ int at(int t) { return t + (t >> PS); }
+};
+
 // insert a zero bit at position b
 __device__ __forceinline__ int ins0(int v, int b) { return ((v >> b) << (b + 1)) | (v & ((1 << b) - 1)); }
 
@@ -175,9 +186,9 @@ __device__ __forceinline__ T product_amp(const T* u, int n, long long x) {
 template <typename R, bool TANG>
 __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   using T = typename CT<R>::T;
-  constexpr int TSMAX = 1 << kMaxTileBits;
-  __shared__ T sP[TSMAX];
-  __shared__ T sD[TANG ? TSMAX : 1];
+  using LD = Lds<T>;
+  __shared__ T sP[LD::TSP];
+  __shared__ T sD[TANG ? LD::TSP : 1];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sRed[kThreads / 64][4];
 
@@ -217,8 +228,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int t = tid + j * kThreads;
         if (t < TS) {
-          sP[t] = product_amp(sU, n, base - (long long)s * dim + xa[j]);
-          if (TANG) sD[t] = cz<T>();
+          sP[LD::at(t)] = product_amp(sU, n, base - (long long)s * dim + xa[j]);
+          if (TANG) sD[LD::at(t)] = cz<T>();
         }
       }
     } else {
@@ -226,8 +237,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int t = tid + j * kThreads;
         if (t < TS) {
-          sP[t] = srcP[base + xa[j]];
-          if (TANG) sD[t] = srcD[base + xa[j]];
+          sP[LD::at(t)] = srcP[base + xa[j]];
+          if (TANG) sD[LD::at(t)] = srcD[base + xa[j]];
         }
       }
     }
@@ -241,6 +252,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         const int t0 = ins0(ins0(tid, lo), hi);
         int ix[4];
         ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
         T p[4], d[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) { p[i] = sP[ix[i]]; if (TANG) d[i] = sD[ix[i]]; }
@@ -258,11 +271,11 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         const int t = tid + j * kThreads;
         if (t < TS) {
           const T ph = phi0[base + xa[j]];
-          const T ps = sP[t];
+          const T ps = sP[LD::at(t)];
           tr += (double)ph.x * ps.x + (double)ph.y * ps.y;
           ti += (double)ph.x * ps.y - (double)ph.y * ps.x;
           if (TANG) {
-            const T dp = sD[t];
+            const T dp = sD[LD::at(t)];
             orr += (double)ph.x * dp.x + (double)ph.y * dp.y;
             oi += (double)ph.x * dp.y - (double)ph.y * dp.x;
           }
@@ -289,8 +302,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int t = tid + j * kThreads;
         if (t < TS) {
-          dstP[base + xa[j]] = sP[t];
-          if (TANG) dstD[base + xa[j]] = sD[t];
+          dstP[base + xa[j]] = sP[LD::at(t)];
+          if (TANG) dstD[base + xa[j]] = sD[LD::at(t)];
         }
       }
     }
@@ -313,11 +326,13 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   using T = typename CT<R>::T;
   using M = Mfma<R>;
   using acc_t = typename M::acc_t;
-  constexpr int TSMAX = 1 << kMaxTileBits;
+  using LD = Lds<T>;
+  constexpr int TSMAX = LD::TSMAX, TSP = LD::TSP;
   constexpr int NST = TANG ? 2 : 1;
-  // sX: forward states (psi | dpsi), sY: backward states (a | b); element t of state st at [st*TSMAX + t]
-  __shared__ T sX[NST * TSMAX];
-  __shared__ T sY[NST * TSMAX];
+  // sX: forward states (psi | dpsi), sY: backward states (a | b); element t of state st at
+  // [st*TSP + LD::at(t)]
+  __shared__ T sX[NST * TSP];
+  __shared__ T sY[NST * TSP];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sM[16 * 16];
 
@@ -351,7 +366,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   // Without tangent states the b rows / dpsi columns only feed the unused D sums; those lanes read
   // the a / psi arrays (in bounds) and their products are discarded.
   const int g_lane = wave * 64 + sub;                 // group of chunk 0
-  const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSMAX + cri;  // in units of R
+  const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSP + cri;  // in units of R
 
   acc_t acc[kMaxGates];
   double accd[kMaxGates][4];
@@ -363,8 +378,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   // Groups g >= ngroups (only when mb < kMaxTileBits) map to tile indices >= 2^mb, which no tile
   // operation writes: zero them once so that their MFMA operands are zero.
   for (int t = TS + tid; t < TSMAX; t += kThreads) {
-    sX[t] = cz<T>(); sY[t] = cz<T>();
-    if (TANG) { sX[TSMAX + t] = cz<T>(); sY[TSMAX + t] = cz<T>(); }
+    sX[LD::at(t)] = cz<T>(); sY[LD::at(t)] = cz<T>();
+    if (TANG) { sX[TSP + LD::at(t)] = cz<T>(); sY[TSP + LD::at(t)] = cz<T>(); }
   }
   __syncthreads();
 
@@ -387,8 +402,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
         const int t = tid + j * kThreads;
         if (t < TS) {
           const T ph = phi0[base + xa[j]];
-          sY[t] = cmul(Ts, ph);
-          if (TANG) sY[TSMAX + t] = cmul(Os, ph);
+          sY[LD::at(t)] = cmul(Ts, ph);
+          if (TANG) sY[TSP + LD::at(t)] = cmul(Os, ph);
         }
       }
     } else {
@@ -396,8 +411,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int t = tid + j * kThreads;
         if (t < TS) {
-          sY[t] = abA[base + xa[j]];
-          if (TANG) sY[TSMAX + t] = abB[base + xa[j]];
+          sY[LD::at(t)] = abA[base + xa[j]];
+          if (TANG) sY[TSP + LD::at(t)] = abB[base + xa[j]];
         }
       }
     }
@@ -409,8 +424,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int t = tid + j * kThreads;
         if (t < TS) {
-          sX[t] = product_amp(sU, n, base - sbase + xa[j]);
-          if (TANG) sX[TSMAX + t] = cz<T>();
+          sX[LD::at(t)] = product_amp(sU, n, base - sbase + xa[j]);
+          if (TANG) sX[TSP + LD::at(t)] = cz<T>();
         }
       }
     } else {
@@ -418,8 +433,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int t = tid + j * kThreads;
         if (t < TS) {
-          sX[t] = srcP[base + xa[j]];
-          if (TANG) sX[TSMAX + t] = srcD[base + xa[j]];
+          sX[LD::at(t)] = srcP[base + xa[j]];
+          if (TANG) sX[TSP + LD::at(t)] = srcD[base + xa[j]];
         }
       }
     }
@@ -431,10 +446,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     for (int j = 0; j < kMaxGates; ++j) {
       if (j < ng) {
         const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
-        // element offset of chunk c = sum over the 4 bits of 4c of their inserted positions (uniform)
-        const int p0 = 1 << grp_bit_pos(2, lo, hi), p1 = 1 << grp_bit_pos(3, lo, hi);
-        const int p2 = 1 << grp_bit_pos(4, lo, hi), p3 = 1 << grp_bit_pos(5, lo, hi);
-        const int tl = ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi);
+        // padded element offset of chunk c = sum over the 4 bits of 4c of their (padded) inserted
+        // positions; wave-uniform, and disjoint in bits from this lane's part tl
+        const int p0 = LD::at(1 << grp_bit_pos(2, lo, hi)), p1 = LD::at(1 << grp_bit_pos(3, lo, hi));
+        const int p2 = LD::at(1 << grp_bit_pos(4, lo, hi)), p3 = LD::at(1 << grp_bit_pos(5, lo, hi));
+        const int tl = LD::at(ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi));
         const R* xs = (const R*)sX + lane_scalar_off + 2 * tl;
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -448,12 +464,14 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
             const int t0 = ins0(ins0(tid, lo), hi);
             int ix[4];
             ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
             T p[4], d[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSMAX + ix[i]]; }
+            for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
             apply_w<T, TANG>(Gk, Vk, p, d);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSMAX + ix[i]] = d[i]; }
+            for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSP + ix[i]] = d[i]; }
           }
           __syncthreads();
         }
@@ -465,9 +483,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     for (int j = kMaxGates - 1; j >= 0; --j) {
       if (j < ng) {
         const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
-        const int p0 = 1 << grp_bit_pos(2, lo, hi), p1 = 1 << grp_bit_pos(3, lo, hi);
-        const int p2 = 1 << grp_bit_pos(4, lo, hi), p3 = 1 << grp_bit_pos(5, lo, hi);
-        const int tl = ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi);
+        const int p0 = LD::at(1 << grp_bit_pos(2, lo, hi)), p1 = LD::at(1 << grp_bit_pos(3, lo, hi));
+        const int p2 = LD::at(1 << grp_bit_pos(4, lo, hi)), p3 = LD::at(1 << grp_bit_pos(5, lo, hi));
+        const int tl = LD::at(ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi));
         const R* ys = (const R*)sY + lane_scalar_off + 2 * tl;
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -480,12 +498,14 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           const int t0 = ins0(ins0(tid, lo), hi);
           int ix[4];
           ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
           T pa[4], pb[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSMAX + ix[i]]; }
+          for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSP + ix[i]]; }
           apply_wdag<T, TANG>(Gk, Vk, pa, pb);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSMAX + ix[i]] = pb[i]; }
+          for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
         }
         __syncthreads();
       }
@@ -505,8 +525,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       for (int j = 0; j < 4; ++j) {
         const int t = tid + j * kThreads;
         if (t < TS) {
-          abA[base + xa[j]] = sY[t];
-          if (TANG) abB[base + xa[j]] = sY[TSMAX + t];
+          abA[base + xa[j]] = sY[LD::at(t)];
+          if (TANG) abB[base + xa[j]] = sY[TSP + LD::at(t)];
         }
       }
     }
