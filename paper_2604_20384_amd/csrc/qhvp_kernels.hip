@@ -147,15 +147,53 @@ __device__ __forceinline__ int opaque_int(int v) {
   return v;
 }
 
-// Padded LDS index of tile element t: one spare element after every 256-byte row, so that the
-// power-of-two strides of gates on low tile bits spread over all banks.  Additive over index
-// values with disjoint bits (used to split MFMA operand addresses into lane + uniform parts).
+// Padded LDS index of tile element t: 16 spare bytes after every 256-byte row, so that the
+// power-of-two strides of gates on low tile bits spread over the banks while 16-byte vector
+// accesses stay aligned.  Additive over index values with disjoint bits (used to split MFMA
+// operand addresses into a per-lane and a wave-uniform part).
 template <typename T> struct Lds {
   static constexpr int PS = sizeof(T) == 8 ? 5 : 4;                      // log2(elements per 256 B)
+  static constexpr int PAD = 16 / (int)sizeof(T);                        // elements of padding per row
   static constexpr int TSMAX = 1 << kMaxTileBits;
   // padded size of one state array, +32 bytes so that a second state array starts 8 banks over
-  static constexpr int TSP = TSMAX + (TSMAX >> PS) + 32 / (int)sizeof(T);
-  static __device__ __forceinline__ int at(int t) { return t + (t >> PS); }
+  static constexpr int TSP = TSMAX + (TSMAX >> PS) * PAD + 32 / (int)sizeof(T);
+  static __device__ __forceinline__ int at(int t) { return t + (t >> PS) * PAD; }
+};
+
+// Global <-> LDS transfer of one state of a tile in 16-byte vectors: thread tid moves tile
+// elements EPV*(tid + kThreads*v) .. +EPV-1 for v < NV.  Tile bit 0 is always statevector bit 0,
+// so those elements are adjacent in memory.  Loads are unconditional: indices beyond a tile of
+// fewer than 2^kMaxTileBits elements alias to in-tile elements (deposit ignores bits >= mb), so
+// every address is in bounds and all loads can be in flight together; only the LDS writes and
+// global stores of such indices are skipped.
+template <typename T> struct TileIO {
+  using V = typename std::conditional<sizeof(T) == 8, float4, double2>::type;
+  static constexpr int EPV = 16 / (int)sizeof(T);
+  static constexpr int NV = (1 << kMaxTileBits) / EPV / kThreads;
+  static __device__ __forceinline__ int elem(int tid, int v) { return EPV * (tid + kThreads * v); }
+  // LDS slot of tile element t, or for t >= TS the (never read) padding slot after row 0; the
+  // write is then unconditional, which keeps the loads from being sunk into guarded blocks.
+  static __device__ __forceinline__ int slot(int t, int TS) { return t < TS ? Lds<T>::at(t) : (1 << Lds<T>::PS); }
+  static __device__ __forceinline__ void load(T* lds, const T* g, long long base, const int* xv, int TS, int tid) {
+    V r[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r[v] = *(const V*)(g + base + xv[v]);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) *(V*)(lds + slot(elem(tid, v), TS)) = r[v];
+  }
+  static __device__ __forceinline__ void store(T* g, const T* lds, long long base, const int* xv, int TS, int tid) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const V r = *(const V*)(lds + Lds<T>::at(elem(tid, v)));
+      if (elem(tid, v) < TS) *(V*)(g + base + xv[v]) = r;
+    }
+  }
+  static __device__ __forceinline__ T part(const V& r, int e) {
+    T o;
+    if constexpr (sizeof(T) == 8) { o.x = e ? r.z : r.x; o.y = e ? r.w : r.y; }
+    else { o.x = r.x; o.y = r.y; }
+    return o;
+  }
 };
 
 // insert a zero bit at position b
@@ -187,8 +225,9 @@ template <typename R, bool TANG>
 __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   using T = typename CT<R>::T;
   using LD = Lds<T>;
-  __shared__ T sP[LD::TSP];
-  __shared__ T sD[TANG ? LD::TSP : 1];
+  using IO = TileIO<T>;
+  __shared__ __attribute__((aligned(16))) T sP[LD::TSP];
+  __shared__ __attribute__((aligned(16))) T sD[TANG ? LD::TSP : 1];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sRed[kThreads / 64][4];
 
@@ -210,9 +249,9 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   const bool gen = (srcP == nullptr);
   const bool ovl = (a.ov_part != nullptr);
 
-  long long xa[4];
+  int xv[IO::NV];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) xa[j] = deposit(tid + j * kThreads, pd.abit, mb);
+  for (int v = 0; v < IO::NV; ++v) xv[v] = (int)deposit(IO::elem(tid, v), pd.abit, mb);
 
   const long long it0 = items * blockIdx.x / gridDim.x;
   const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
@@ -220,27 +259,24 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   for (long long it = it0; it < it1; ++it) {
     const int s = (int)(it / tiles);
     const int w = (int)(it - (long long)s * tiles);
-    const long long base = (long long)s * dim + deposit(w, pd.ibit, n - mb);
+    const long long sbase = (long long)s * dim;
+    const long long base = sbase + deposit(w, pd.ibit, n - mb);
     if (gen) {
       if (tid < 2 * n) sU[tid] = samp[(long long)s * 2 * n + tid];
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          sP[LD::at(t)] = product_amp(sU, n, base - (long long)s * dim + xa[j]);
-          if (TANG) sD[LD::at(t)] = cz<T>();
-        }
-      }
-    } else {
+      for (int v = 0; v < IO::NV; ++v)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          sP[LD::at(t)] = srcP[base + xa[j]];
-          if (TANG) sD[LD::at(t)] = srcD[base + xa[j]];
+        for (int e = 0; e < IO::EPV; ++e) {
+          const int t = IO::elem(tid, v) + e;
+          if (t < TS) {
+            sP[LD::at(t)] = product_amp(sU, n, base - sbase + xv[v] + e);
+            if (TANG) sD[LD::at(t)] = cz<T>();
+          }
         }
-      }
+    } else {
+      IO::load(sP, srcP, base, xv, TS, tid);
+      if (TANG) IO::load(sD, srcD, base, xv, TS, tid);
     }
     __syncthreads();
 
@@ -266,21 +302,26 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
 
     if (ovl) {
       double tr = 0, ti = 0, orr = 0, oi = 0;
+      typename IO::V ph[IO::NV];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          const T ph = phi0[base + xa[j]];
-          const T ps = sP[LD::at(t)];
-          tr += (double)ph.x * ps.x + (double)ph.y * ps.y;
-          ti += (double)ph.x * ps.y - (double)ph.y * ps.x;
-          if (TANG) {
-            const T dp = sD[LD::at(t)];
-            orr += (double)ph.x * dp.x + (double)ph.y * dp.y;
-            oi += (double)ph.x * dp.y - (double)ph.y * dp.x;
+      for (int v = 0; v < IO::NV; ++v) ph[v] = *(const typename IO::V*)(phi0 + base + xv[v]);
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v)
+#pragma unroll
+        for (int e = 0; e < IO::EPV; ++e) {
+          const int t = IO::elem(tid, v) + e;
+          if (t < TS) {
+            const T f = IO::part(ph[v], e);
+            const T ps = sP[LD::at(t)];
+            tr += (double)f.x * ps.x + (double)f.y * ps.y;
+            ti += (double)f.x * ps.y - (double)f.y * ps.x;
+            if (TANG) {
+              const T dp = sD[LD::at(t)];
+              orr += (double)f.x * dp.x + (double)f.y * dp.y;
+              oi += (double)f.x * dp.y - (double)f.y * dp.x;
+            }
           }
         }
-      }
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
         tr += __shfl_xor(tr, off);
@@ -298,14 +339,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         a.ov_part[it * 4 + tid] = v;
       }
     } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          dstP[base + xa[j]] = sP[LD::at(t)];
-          if (TANG) dstD[base + xa[j]] = sD[LD::at(t)];
-        }
-      }
+      IO::store(dstP, sP, base, xv, TS, tid);
+      if (TANG) IO::store(dstD, sD, base, xv, TS, tid);
     }
     __syncthreads();
   }
@@ -327,12 +362,13 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   using M = Mfma<R>;
   using acc_t = typename M::acc_t;
   using LD = Lds<T>;
+  using IO = TileIO<T>;
   constexpr int TSMAX = LD::TSMAX, TSP = LD::TSP;
   constexpr int NST = TANG ? 2 : 1;
   // sX: forward states (psi | dpsi), sY: backward states (a | b); element t of state st at
   // [st*TSP + LD::at(t)]
-  __shared__ T sX[NST * TSP];
-  __shared__ T sY[NST * TSP];
+  __shared__ __attribute__((aligned(16))) T sX[NST * TSP];
+  __shared__ __attribute__((aligned(16))) T sY[NST * TSP];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sM[16 * 16];
 
@@ -354,10 +390,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   const T* __restrict__ samp = (const T*)a.samples;
   const bool gen = (srcP == nullptr);
 
-  int xa[4];
+  int xv[IO::NV];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) xa[j] = (int)deposit(tid + j * kThreads, pd.abit, mb);
-
+  for (int v = 0; v < IO::NV; ++v) xv[v] = (int)deposit(IO::elem(tid, v), pd.abit, mb);
 
   // MFMA operand of this lane: real part cri of amplitude cidx (pair index 2*b_hi + b_lo) of state
   // cst, for group wave*64 + 4*c + sub in chunk c (A: rows = lane%16, B: columns = lane%16).
@@ -392,51 +427,65 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     const long long sbase = (long long)s * dim;
     const long long base = sbase + deposit(w, pd.ibit, n - mb);
 
+    if (!a.fold && !gen) {
+      // common case: all four states come from memory; put every load in flight before any write
+      typename IO::V r[4][IO::NV];
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v) {
+        r[0][v] = *(const typename IO::V*)(abA + base + xv[v]);
+        if (TANG) r[1][v] = *(const typename IO::V*)(abB + base + xv[v]);
+        r[2][v] = *(const typename IO::V*)(srcP + base + xv[v]);
+        if (TANG) r[3][v] = *(const typename IO::V*)(srcD + base + xv[v]);
+      }
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v) {
+        const int sl = IO::slot(IO::elem(tid, v), TS);
+        *(typename IO::V*)(sY + sl) = r[0][v];
+        if (TANG) *(typename IO::V*)(sY + TSP + sl) = r[1][v];
+        *(typename IO::V*)(sX + sl) = r[2][v];
+        if (TANG) *(typename IO::V*)(sX + TSP + sl) = r[3][v];
+      }
+    } else {
     // ---- backward states (a, b) at the pass output
     if (a.fold) {
       T Ts, Os;
       Ts.x = (R)a.tov[4 * s + 0]; Ts.y = (R)a.tov[4 * s + 1];
       Os.x = (R)a.tov[4 * s + 2]; Os.y = (R)a.tov[4 * s + 3];
+      typename IO::V ph[IO::NV];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          const T ph = phi0[base + xa[j]];
-          sY[LD::at(t)] = cmul(Ts, ph);
-          if (TANG) sY[TSP + LD::at(t)] = cmul(Os, ph);
+      for (int v = 0; v < IO::NV; ++v) ph[v] = *(const typename IO::V*)(phi0 + base + xv[v]);
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v)
+#pragma unroll
+        for (int e = 0; e < IO::EPV; ++e) {
+          const int t = IO::elem(tid, v) + e;
+          const int at = t < TS ? LD::at(t) : (1 << LD::PS) + e;    // padding slot when outside the tile
+          const T f = IO::part(ph[v], e);
+          sY[at] = cmul(Ts, f);
+          if (TANG) sY[TSP + at] = cmul(Os, f);
         }
-      }
     } else {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          sY[LD::at(t)] = abA[base + xa[j]];
-          if (TANG) sY[TSP + LD::at(t)] = abB[base + xa[j]];
-        }
-      }
+      IO::load(sY, abA, base, xv, TS, tid);
+      if (TANG) IO::load(sY + TSP, abB, base, xv, TS, tid);
     }
     // ---- forward states (psi, dpsi) at the pass input
     if (gen) {
       if (tid < 2 * n) sU[tid] = samp[(long long)s * 2 * n + tid];
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          sX[LD::at(t)] = product_amp(sU, n, base - sbase + xa[j]);
-          if (TANG) sX[TSP + LD::at(t)] = cz<T>();
-        }
-      }
-    } else {
+      for (int v = 0; v < IO::NV; ++v)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          sX[LD::at(t)] = srcP[base + xa[j]];
-          if (TANG) sX[TSP + LD::at(t)] = srcD[base + xa[j]];
+        for (int e = 0; e < IO::EPV; ++e) {
+          const int t = IO::elem(tid, v) + e;
+          if (t < TS) {
+            sX[LD::at(t)] = product_amp(sU, n, base - sbase + xv[v] + e);
+            if (TANG) sX[TSP + LD::at(t)] = cz<T>();
+          }
         }
-      }
+    } else {
+      IO::load(sX, srcP, base, xv, TS, tid);
+      if (TANG) IO::load(sX + TSP, srcD, base, xv, TS, tid);
+    }
     }
     __syncthreads();
 
@@ -521,14 +570,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     }
 
     if (a.store_ab) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int t = tid + j * kThreads;
-        if (t < TS) {
-          abA[base + xa[j]] = sY[LD::at(t)];
-          if (TANG) abB[base + xa[j]] = sY[TSP + LD::at(t)];
-        }
-      }
+      IO::store(abA, sY, base, xv, TS, tid);
+      if (TANG) IO::store(abB, sY + TSP, base, xv, TS, tid);
     }
     __syncthreads();
   }
