@@ -32,6 +32,8 @@ def parse():
     ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
     ap.add_argument("--ckpt", type=int, default=1, help="layer checkpoint interval (0: every pass boundary)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=40)
     ap.add_argument("--seed", type=int, default=1)
     return ap.parse_args()
 
@@ -51,6 +53,38 @@ def cpu_baseline(n, L, seed):
     dt = time.perf_counter() - t0
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     return dt, threads
+
+
+def serving(n_req, seed):
+    """Poisson stream of mixed grad / HVP requests (complex64) at 0.9x the measured serial
+    capacity, served one at a time (FIFO) and with continuous batching over 4 streams."""
+    import numpy as np
+
+    from paper_2604_20384_amd import serve
+
+    rng = np.random.default_rng(seed)
+    reqs = [serve.random_request(rng, n_range=(10, 20), L_range=(4, 16), ns_range=(16, 128))
+            for _ in range(n_req)]
+    # warm-up (first launches, allocator)
+    w = serve.Server(serve.GpuExecutor(), slots=1)
+    w.submit(reqs[0]).result()
+    w.shutdown()
+    # serial capacity: all requests queued at once, one slot
+    srv = serve.Server(serve.GpuExecutor(), slots=1)
+    res, t0, t1 = serve.replay(srv, reqs, np.zeros(n_req))
+    srv.shutdown()
+    mu = n_req / (t1 - t0)
+    lam = 0.9 * mu
+    arrivals = serve.poisson_arrivals(rng, lam, n_req)
+    out = {"requests": n_req, "n": [10, 20], "L": [4, 16], "N_s": [16, 128], "precision": "c64",
+           "serial_capacity_rps": round(mu, 3), "arrival_rate_rps": round(lam, 3)}
+    for name, slots in (("serial", 1), ("batched", 4)):
+        srv = serve.Server(serve.GpuExecutor(), slots=slots)
+        res, t0, t1 = serve.replay(srv, reqs, arrivals)
+        srv.shutdown()
+        rep = serve.latency_report(res, t0, t1)
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in rep.items()}
+    return out
 
 
 def main():
@@ -140,6 +174,10 @@ def main():
     gp.close()
     del gp
     torch.cuda.empty_cache()
+    if not args.no_serving:
+        out["serving"] = serving(args.serve_requests, args.seed)
+        out["served_p50_s"] = out["serving"]["batched"]["p50_s"]
+        out["served_p99_s"] = out["serving"]["batched"]["p99_s"]
     if not args.no_cpu_baseline:
         t_sample, threads = cpu_baseline(n, L, args.seed)
         out["cpu_baseline"] = {"value": 1.0 / (ns * t_sample), "unit": "HVP/s", "cores": threads,

@@ -126,6 +126,17 @@ qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom,
 qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom,
                      double* cost, double* grad, double* hvp);
 
+/* Two-phase form of qhvp_grad / qhvp_hvp (Alg. 1: forward pass, then backward pass).
+ * qhvp_forward runs the forward sweep at G (with the tangent sweep along V if V != NULL; V is
+ * projected onto the tangent space first when geom is Riemannian), returns the cost and
+ * fidelity, and keeps the layer checkpoints in the workspace.  qhvp_backward then runs the
+ * backward sweep of that forward sweep once and returns the gradient (and, if the forward had a
+ * direction, the HVP; either pointer may be NULL).  A second qhvp_backward without a new
+ * qhvp_forward fails with QHVP_ERR_INVALID. */
+qhvp_status qhvp_forward(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom,
+                         double* cost, double* fidelity);
+qhvp_status qhvp_backward(qhvp_problem* p, double* grad, double* hvp);
+
 /* Per-sample overlaps T_s and Omega_s = D(T_s)[V] (n_samples complex each, host) of
  * the last cost/grad/hvp call (Omega is zero unless that call was an HVP). */
 qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega);
@@ -134,7 +145,7 @@ qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega);
 qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size_t* ws_bytes,
                               int* segments);
 
-/* Milliseconds spent on the device by the last call (HIP events around it). */
+/* Milliseconds spent on the device by the last cost / forward(+backward) evaluation (HIP events). */
 double qhvp_last_device_ms(const qhvp_problem* p);
 
 /* ---- per-kernel timing (HIP events around every launch on the problem's stream) ---- */

@@ -111,6 +111,7 @@ class Problem:
                                       1 if with_tangent else 0, ws_ptr, self.ws_bytes,
                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.handle = h
+        self.epoch = 0          # bumped by every device evaluation (checkpoints are overwritten)
 
     def _layers_of(self, K_ref):
         for Lr in range(1, 10000):
@@ -120,12 +121,14 @@ class Problem:
 
     # ------------------------------------------------------------------
     def cost(self, G):
+        self.epoch += 1
         G = _c128(G, (self.K, 4, 4))
         c, f = C.c_double(), C.c_double()
         check(lib.qhvp_cost(self.handle, dptr(_f64(G)), C.byref(c), C.byref(f)))
         return c.value, f.value
 
     def grad(self, G, riemannian=False):
+        self.epoch += 1
         G = _c128(G, (self.K, 4, 4))
         g = np.empty((self.K, 4, 4), dtype=np.complex128)
         c = C.c_double()
@@ -133,6 +136,7 @@ class Problem:
         return c.value, g
 
     def hvp(self, G, V, riemannian=False):
+        self.epoch += 1
         G = _c128(G, (self.K, 4, 4))
         V = _c128(V, (self.K, 4, 4))
         g = np.empty((self.K, 4, 4), dtype=np.complex128)
@@ -141,6 +145,24 @@ class Problem:
         check(lib.qhvp_hvp(self.handle, dptr(_f64(G)), dptr(_f64(V)), int(riemannian), C.byref(c),
                            dptr(_f64(g)), dptr(_f64(h))))
         return c.value, g, h
+
+    def forward(self, G, V=None, riemannian=False):
+        """Forward sweep (keeps the checkpoints for one `backward`); returns (cost, fidelity)."""
+        self.epoch += 1
+        G = _c128(G, (self.K, 4, 4))
+        Vp = None if V is None else dptr(_f64(_c128(V, (self.K, 4, 4))))
+        c, f = C.c_double(), C.c_double()
+        check(lib.qhvp_forward(self.handle, dptr(_f64(G)), Vp, int(riemannian), C.byref(c), C.byref(f)))
+        self._fwd_tangent = V is not None
+        return c.value, f.value
+
+    def backward(self):
+        """Backward sweep of the last `forward`; returns grad, or (grad, hvp) after a forward with V."""
+        self.epoch += 1
+        g = np.empty((self.K, 4, 4), dtype=np.complex128)
+        h = np.empty((self.K, 4, 4), dtype=np.complex128) if getattr(self, "_fwd_tangent", False) else None
+        check(lib.qhvp_backward(self.handle, dptr(_f64(g)), None if h is None else dptr(_f64(h))))
+        return g if h is None else (g, h)
 
     def overlaps(self):
         T = np.empty(self.n_samples, dtype=np.complex128)

@@ -296,6 +296,10 @@ struct qhvp_problem {
   double* h_tov;   // Ns*4
   double* h_env;   // K*64
   std::vector<double> last_T, last_Om;
+  // two-phase evaluation: a forward sweep leaves its checkpoints for one backward sweep
+  int fwd_ready = 0, fwd_tangent = 0;
+  qhvp_geometry fwd_geom = QHVP_EUCLIDEAN;
+  std::vector<double> fwd_G, fwd_V;
   hipEvent_t ev0, ev1;
   double last_ms;
   // optional per-launch timing: events bracket every launch of the call; stats accumulate per kind
@@ -515,8 +519,26 @@ qhvp_status check_gates(const qhvp_problem* p, const double* G, const char* what
   return QHVP_OK;
 }
 
-qhvp_status run(qhvp_problem* p, const double* G, const double* V, int mode /*0 cost,1 grad,2 hvp*/) {
+qhvp_status finish_call(qhvp_problem* p, int copy_env, int tangent) {
+  if (copy_env)
+    HIP_TRY(hipMemcpyAsync(p->h_env, p->small(p->lay.o_env), (size_t)p->K * qhvp::kEnvVals * sizeof(double),
+                           hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipEventRecord(p->ev1, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
+  p->last_ms += ms;
+  HIP_TRY(prof_collect(p));
+  (void)tangent;
+  return QHVP_OK;
+}
+
+// Forward phase.  mode 0: cost only (no checkpoints kept); 1: gradient sweep; 2: HVP sweep.  Uploads
+// G (and V), sweeps, and brings the per-sample overlaps T_s (and Omega_s) back to the host.
+qhvp_status phase_forward(qhvp_problem* p, const double* G, const double* V, int mode) {
   HIP_TRY(hipSetDevice(p->ctx->device));
+  p->fwd_ready = 0;
+  p->last_ms = 0;
   to_device_precision(p, G, (size_t)p->K * 16, p->h_gates);
   HIP_TRY(hipEventRecord(p->ev0, p->stream));
   HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_gates), p->h_gates, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
@@ -525,35 +547,38 @@ qhvp_status run(qhvp_problem* p, const double* G, const double* V, int mode /*0 
     HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_dirs), p->h_dirs, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
   }
   const int tangent = mode == 2 ? 1 : 0;
-  qhvp_status st;
-  if (mode == 0) {
-    st = forward_sweep(p, p->passes, p->small(p->lay.o_gates), nullptr, 0, 2);
-    if (st) return st;
-  } else {
-    st = forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent, 1);
-    if (st) return st;
-    st = backward_sweep(p, tangent);
-    if (st) return st;
-    HIP_TRY(hipMemcpyAsync(p->h_env, p->small(p->lay.o_env), (size_t)p->K * qhvp::kEnvVals * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  }
+  qhvp_status st = mode == 0 ? forward_sweep(p, p->passes, p->small(p->lay.o_gates), nullptr, 0, 2)
+                             : forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent, 1);
+  if (st) return st;
   HIP_TRY(hipMemcpyAsync(p->h_tov, p->small(p->lay.o_tov), (size_t)p->Ns * 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipEventRecord(p->ev1, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-  p->last_ms = ms;
-  HIP_TRY(prof_collect(p));
+  st = finish_call(p, 0, tangent);
+  if (st) return st;
   p->last_T.assign(2 * p->Ns, 0.0);
   p->last_Om.assign(2 * p->Ns, 0.0);
   for (int s = 0; s < p->Ns; ++s) {
     p->last_T[2 * s] = p->h_tov[4 * s];
     p->last_T[2 * s + 1] = p->h_tov[4 * s + 1];
-    if (mode == 2) {
+    if (tangent) {
       p->last_Om[2 * s] = p->h_tov[4 * s + 2];
       p->last_Om[2 * s + 1] = p->h_tov[4 * s + 3];
     }
   }
+  if (mode != 0) {
+    p->fwd_ready = 1;
+    p->fwd_tangent = tangent;
+  }
   return QHVP_OK;
+}
+
+// Backward phase of the last gradient / HVP forward phase (its checkpoints are consumed).
+qhvp_status phase_backward(qhvp_problem* p) {
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  if (!p->fwd_ready) return fail(QHVP_ERR_INVALID, "no forward sweep to differentiate (call qhvp_forward first)");
+  p->fwd_ready = 0;
+  HIP_TRY(hipEventRecord(p->ev0, p->stream));
+  qhvp_status st = backward_sweep(p, p->fwd_tangent);
+  if (st) return st;
+  return finish_call(p, 1, p->fwd_tangent);
 }
 
 // Alg. 2 post-processing over samples: F = mean |T_s|^2; with the folded environments
@@ -698,7 +723,7 @@ qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fi
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
   qhvp_status st = check_gates(p, G, "G");
   if (st) return st;
-  st = run(p, G, nullptr, 0);
+  st = phase_forward(p, G, nullptr, 0);
   if (st) return st;
   const double F = fidelity_of(p);
   if (cost) *cost = 1.0 - F;
@@ -706,52 +731,74 @@ qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fi
   return QHVP_OK;
 }
 
-qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom, double* cost, double* grad) {
+qhvp_status qhvp_forward(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
+                         double* fidelity) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
-  if (!grad) return fail(QHVP_ERR_INVALID, "grad is NULL");
   if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
   qhvp_status st = check_gates(p, G, "G");
   if (st) return st;
+  if (V) {
+    if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
+    st = check_gates(p, V, "V");
+    if (st) return st;
+  }
   if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->K, G) > 1e-10)
     return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
-  st = run(p, G, nullptr, 1);
+  p->fwd_G.assign(G, G + (size_t)p->K * 32);
+  p->fwd_V.clear();
+  if (V) {
+    p->fwd_V.assign(V, V + (size_t)p->K * 32);
+    // the Riemannian HVP formula assumes a tangent direction: project V first
+    if (geom == QHVP_RIEMANNIAN) qhvp_project(p->K, G, V, p->fwd_V.data());
+  }
+  p->fwd_geom = geom;
+  st = phase_forward(p, G, V ? p->fwd_V.data() : nullptr, V ? 2 : 1);
   if (st) return st;
-  if (cost) *cost = 1.0 - fidelity_of(p);
-  std::vector<double> g((size_t)p->K * 32);
-  env_to_output(p, 0, g.data());
-  if (geom == QHVP_RIEMANNIAN) return qhvp_project(p->K, G, g.data(), grad);
-  std::memcpy(grad, g.data(), g.size() * sizeof(double));
+  const double F = fidelity_of(p);
+  if (cost) *cost = 1.0 - F;
+  if (fidelity) *fidelity = F;
   return QHVP_OK;
+}
+
+qhvp_status qhvp_backward(qhvp_problem* p, double* grad, double* hvp) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (!p->fwd_ready) return fail(QHVP_ERR_INVALID, "no forward sweep to differentiate (call qhvp_forward first)");
+  if (hvp && !p->fwd_tangent) return fail(QHVP_ERR_INVALID, "the last forward sweep had no direction V");
+  const int tangent = p->fwd_tangent;
+  qhvp_status st = phase_backward(p);
+  if (st) return st;
+  std::vector<double> g((size_t)p->K * 32), h;
+  env_to_output(p, 0, g.data());
+  if (tangent) {
+    h.resize((size_t)p->K * 32);
+    env_to_output(p, 1, h.data());
+  }
+  if (p->fwd_geom == QHVP_RIEMANNIAN) {
+    if (grad) qhvp_project(p->K, p->fwd_G.data(), g.data(), grad);
+    if (hvp) return qhvp_riemannian_hvp(p->K, p->fwd_G.data(), g.data(), h.data(), p->fwd_V.data(), hvp);
+    return QHVP_OK;
+  }
+  if (grad) std::memcpy(grad, g.data(), g.size() * sizeof(double));
+  if (hvp) std::memcpy(hvp, h.data(), h.size() * sizeof(double));
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom, double* cost, double* grad) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (!grad) return fail(QHVP_ERR_INVALID, "grad is NULL");
+  qhvp_status st = qhvp_forward(p, G, nullptr, geom, cost, nullptr);
+  if (st) return st;
+  return qhvp_backward(p, grad, nullptr);
 }
 
 qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
                      double* grad, double* hvp) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
   if (!hvp) return fail(QHVP_ERR_INVALID, "hvp is NULL");
-  if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
-  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
-  qhvp_status st = check_gates(p, G, "G");
+  if (!V) return fail(QHVP_ERR_INVALID, "V is NULL");
+  qhvp_status st = qhvp_forward(p, G, V, geom, cost, nullptr);
   if (st) return st;
-  st = check_gates(p, V, "V");
-  if (st) return st;
-  std::vector<double> Vt(V, V + (size_t)p->K * 32);
-  if (geom == QHVP_RIEMANNIAN) {
-    if (qhvp_unitarity_error(p->K, G) > 1e-10) return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
-    qhvp_project(p->K, G, V, Vt.data());   // the Riemannian HVP formula assumes a tangent direction
-  }
-  st = run(p, G, Vt.data(), 2);
-  if (st) return st;
-  if (cost) *cost = 1.0 - fidelity_of(p);
-  std::vector<double> g((size_t)p->K * 32), h((size_t)p->K * 32);
-  env_to_output(p, 0, g.data());
-  env_to_output(p, 1, h.data());
-  if (geom == QHVP_RIEMANNIAN) {
-    if (grad) qhvp_project(p->K, G, g.data(), grad);
-    return qhvp_riemannian_hvp(p->K, G, g.data(), h.data(), Vt.data(), hvp);
-  }
-  if (grad) std::memcpy(grad, g.data(), g.size() * sizeof(double));
-  std::memcpy(hvp, h.data(), h.size() * sizeof(double));
-  return QHVP_OK;
+  return qhvp_backward(p, grad, hvp);
 }
 
 qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega) {

@@ -1,0 +1,103 @@
+"""The differentiable cost (torch.autograd.Function) on the hand-written adjoint sweep."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import circuit, sv
+from paper_2604_20384_amd.inputs import make_problem
+
+
+def test_complex_gradient_convention_cpu():
+    """A custom Function returning grad_out * (f_x + i f_y) reproduces PyTorch's own .grad
+    (App. A convention), so returning grad_out * grad C is right."""
+    class Abs2(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, z):
+            ctx.save_for_backward(z)
+            return (z.conj() * z).real.sum()
+
+        @staticmethod
+        def backward(ctx, go):
+            (z,) = ctx.saved_tensors
+            return go * 2 * z              # grad |z|^2 = 2x + 2iy
+
+    z0 = torch.tensor([1 + 1j, -0.5 + 2j], dtype=torch.complex128)
+    z1 = z0.clone().requires_grad_(True)
+    (3.0 * Abs2.apply(z1)).backward()
+    z2 = z0.clone().requires_grad_(True)
+    (3.0 * (z2.abs() ** 2).sum()).backward()
+    assert torch.allclose(z1.grad, z2.grad)
+
+
+@pytest.mark.gpu
+def test_autograd_matches_library_oracle_and_finite_differences(gpu):
+    """n=18, L=16 (K=136), N_s=128, complex128, checkpoint every 4 layers."""
+    from paper_2604_20384_amd.api import Problem
+    from paper_2604_20384_amd.autograd import hs_cost
+
+    n, L, ns = 18, 16, 128
+    p = make_problem(n, L, ns, seed=4)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
+    gp = Problem(n, L, p.uref, p.samples, L_ref=p.L_ref, precision="c128", ckpt_every=4, with_tangent=False)
+    peak_ckpt = torch.cuda.max_memory_allocated() - base
+
+    G = torch.tensor(p.G, dtype=torch.complex128, device="cuda", requires_grad=True)
+    cost = hs_cost(G, gp)
+    cost.backward()
+    g_auto = G.grad.detach().cpu().numpy()
+    c_lib, g_lib = gp.grad(p.G)
+    assert float(cost) == c_lib
+    assert np.array_equal(g_auto, g_lib)
+
+    # central differences of the fidelity along random directions (step 1e-6)
+    rng = np.random.default_rng(0)
+    h = 1e-6
+    for _ in range(3):
+        D = rng.standard_normal(p.G.shape) + 1j * rng.standard_normal(p.G.shape)
+        Fp = gp.cost(p.G + h * D)[1]
+        Fm = gp.cost(p.G - h * D)[1]
+        fd = -(Fp - Fm) / (2 * h)
+        an = float(np.sum(np.conj(g_auto) * D).real)
+        assert abs(fd - an) <= 1e-6 * abs(an), (fd, an)
+
+    # the oracle gradient on the first 8 samples, against the same function on those samples
+    sub = 8
+    gp8 = Problem(n, L, p.uref, p.samples[:sub], L_ref=p.L_ref, precision="c128", ckpt_every=4,
+                  with_tangent=False)
+    G8 = torch.tensor(p.G, dtype=torch.complex128, device="cuda", requires_grad=True)
+    hs_cost(G8, gp8).backward()
+    psi, phi = circuit.labels(p.uref, p.samples[:sub], n, p.L_ref)
+    ref = sv.evaluate(psi, phi, p.G, None, n, L, batch=8)
+    g8 = G8.grad.cpu().numpy()
+    assert np.linalg.norm(g8 - ref["grad"]) <= 1e-10 * np.linalg.norm(ref["grad"])
+
+    # peak HBM with every pass boundary kept instead of every 4th layer boundary
+    del gp8
+    gp.close()
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    base = torch.cuda.memory_allocated()
+    gp0 = Problem(n, L, p.uref, p.samples, L_ref=p.L_ref, precision="c128", ckpt_every=0, with_tangent=False)
+    peak_all = torch.cuda.max_memory_allocated() - base
+    G0 = torch.tensor(p.G, dtype=torch.complex128, device="cuda", requires_grad=True)
+    hs_cost(G0, gp0).backward()
+    assert np.array_equal(G0.grad.cpu().numpy(), g_auto)       # checkpointing changes no arithmetic
+    print(f"peak HBM: checkpoint every 4 layers {peak_ckpt / 2**30:.2f} GiB, "
+          f"every pass boundary {peak_all / 2**30:.2f} GiB")
+    assert peak_ckpt < 0.5 * peak_all
+
+
+@pytest.mark.gpu
+def test_autograd_recomputes_after_interleaved_use(gpu):
+    from paper_2604_20384_amd.api import Problem
+    from paper_2604_20384_amd.autograd import hs_cost
+    p = make_problem(11, 5, 3, seed=8)
+    gp = Problem(11, 5, p.uref, p.samples, L_ref=p.L_ref, precision="c128", ckpt_every=2)
+    G = torch.tensor(p.G, dtype=torch.complex128, requires_grad=True)
+    c = hs_cost(G, gp)
+    gp.hvp(p.G + 0.1, p.V)            # overwrites the checkpoints of the forward above
+    (2.0 * c).backward()
+    _, g = gp.grad(p.G)
+    assert np.array_equal(G.grad.numpy(), 2.0 * g)

@@ -1,0 +1,154 @@
+"""Serving loop: admission, chunking, overlap, fairness, failures (CPU, with a fake executor);
+results alone vs in the mix and latency report (GPU)."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import circuit, sv
+from paper_2604_20384_amd import serve
+from paper_2604_20384_amd.inputs import make_problem
+
+
+class FakeExecutor:
+    """Computes results with the oracle (small n) and sleeps `delay` seconds per chunk; records
+    how much memory the running requests hold."""
+
+    def __init__(self, delay=0.02, fail_rid=None):
+        from paper_2604_20384_amd.api import workspace_bytes
+        self.bytes_fn = workspace_bytes
+        self.delay = delay
+        self.fail_rid = fail_rid
+        self.lock = threading.Lock()
+        self.running = 0
+        self.max_running = 0
+        self.order = []
+
+    def new_stream(self):
+        return None
+
+    def run_chunk(self, req, lo, hi, ckpt, stream):
+        with self.lock:
+            self.running += 1
+            self.max_running = max(self.max_running, self.running)
+            if lo == 0:
+                self.order.append(req.rid)
+        try:
+            if req.rid == self.fail_rid:
+                raise RuntimeError("injected failure")
+            time.sleep(self.delay)
+            psi, phi = circuit.labels(req.uref, req.samples[lo:hi], req.n, req.L_ref)
+            out = sv.evaluate(psi, phi, req.G, req.V if req.kind == "hvp" else None, req.n, req.L)
+            return out["fidelity"], out["grad"], out.get("hvp")
+        finally:
+            with self.lock:
+                self.running -= 1
+
+
+def _req(n, L, ns, kind, seed):
+    p = make_problem(n, L, ns, seed=seed)
+    return serve.Request(kind, n, L, p.uref, p.samples, p.G, p.V if kind == "hvp" else None, L_ref=p.L_ref,
+                         precision="c128")
+
+
+def test_results_and_fifo_and_overlap():
+    ex = FakeExecutor(delay=0.05)
+    srv = serve.Server(ex, slots=4, memory_budget=1 << 40)
+    reqs = [_req(4 + i % 3, 2 + i % 2, 3, "hvp" if i % 2 else "grad", i) for i in range(12)]
+    t0 = time.perf_counter()
+    futs = [srv.submit(r) for r in reqs]
+    res = [f.result() for f in futs]
+    dt = time.perf_counter() - t0
+    srv.shutdown()
+    assert ex.order == list(range(12))              # started in arrival order
+    assert ex.max_running > 1                       # requests overlapped
+    assert dt < 12 * 0.05                           # faster than one at a time
+    for r, q in zip(res, reqs):
+        psi, phi = circuit.labels(q.uref, q.samples, q.n, q.L_ref)
+        out = sv.evaluate(psi, phi, q.G, q.V, q.n, q.L)
+        assert abs(r.cost - out["cost"]) < 1e-14
+        assert np.allclose(r.grad, out["grad"], atol=1e-15)
+        if q.kind == "hvp":
+            assert np.allclose(r.hvp, out["hvp"], atol=1e-15)
+
+
+def test_memory_admission_never_exceeds_budget():
+    from paper_2604_20384_amd.api import workspace_bytes
+    reqs = [_req(6, 3, 4, "hvp", 100 + i) for i in range(8)]
+    one = workspace_bytes(6, 3, 6, 4, "c128", 0, True)
+    ex = FakeExecutor(delay=0.03)
+    srv = serve.Server(ex, slots=8, memory_budget=2 * one + one // 2, request_cap=one)
+    [f.result() for f in [srv.submit(r) for r in reqs]]
+    srv.shutdown()
+    assert ex.max_running == 2                      # memory, not slots, limits the overlap
+
+
+def test_sample_chunking_matches_unchunked():
+    from paper_2604_20384_amd.api import workspace_bytes
+    q = _req(5, 3, 9, "hvp", 7)
+    full = workspace_bytes(5, 3, 6, 9, "c128", 8, True)
+    cap = workspace_bytes(5, 3, 6, 3, "c128", 0, True)
+    plan = serve.plan_request(q, workspace_bytes, cap)
+    assert len(plan.chunks) > 1 and full > cap
+    assert plan.chunks[0][0] == 0 and plan.chunks[-1][1] == 9
+    srv = serve.Server(FakeExecutor(delay=0.0), slots=2, memory_budget=4 * cap, request_cap=cap)
+    r = srv.submit(q).result()
+    srv.shutdown()
+    psi, phi = circuit.labels(q.uref, q.samples, q.n, q.L_ref)
+    out = sv.evaluate(psi, phi, q.G, q.V, q.n, q.L)
+    assert abs(r.fidelity - out["fidelity"]) < 1e-15
+    assert np.allclose(r.grad, out["grad"], atol=1e-15) and np.allclose(r.hvp, out["hvp"], atol=1e-15)
+
+
+def test_failure_is_isolated():
+    ex = FakeExecutor(delay=0.01, fail_rid=2)
+    srv = serve.Server(ex, slots=2, memory_budget=1 << 40)
+    futs = [srv.submit(_req(4, 2, 2, "grad", i)) for i in range(5)]
+    with pytest.raises(RuntimeError, match="injected"):
+        futs[2].result()
+    assert all(f.result().cost > 0 for i, f in enumerate(futs) if i != 2)
+    srv.shutdown()
+
+
+def test_oversized_request_is_rejected():
+    q = _req(6, 2, 2, "grad", 1)
+    srv = serve.Server(FakeExecutor(), slots=1, memory_budget=1 << 20, request_cap=1 << 10)
+    with pytest.raises(MemoryError):
+        srv.submit(q)
+    srv.shutdown()
+
+
+def test_latency_report_and_poisson():
+    rng = np.random.default_rng(0)
+    arr = serve.poisson_arrivals(rng, rate=50.0, count=2000)
+    assert abs(np.mean(np.diff(arr)) - 1 / 50.0) < 0.002
+    ex = FakeExecutor(delay=0.005)
+    srv = serve.Server(ex, slots=2, memory_budget=1 << 40)
+    reqs = [_req(4, 2, 2, "grad", i) for i in range(10)]
+    res, t0, t1 = serve.replay(srv, reqs, serve.poisson_arrivals(rng, 100.0, 10))
+    srv.shutdown()
+    rep = serve.latency_report(res, t0, t1)
+    assert rep["requests"] == 10 and rep["p99_s"] >= rep["p50_s"] > 0
+
+
+@pytest.mark.gpu
+def test_gpu_results_alone_equal_results_in_the_mix(gpu):
+    """Mixed n / L / N_s grad and HVP requests overlap on four streams; every result is bitwise
+    the result of the same request served alone."""
+    rng = np.random.default_rng(3)
+    reqs = [serve.random_request(rng, n_range=(10, 16), L_range=(2, 8), ns_range=(4, 48)) for _ in range(16)]
+    ex = serve.GpuExecutor()
+    srv = serve.Server(ex, slots=4, memory_budget=64 << 30)
+    res, t0, t1 = serve.replay(srv, reqs, serve.poisson_arrivals(rng, 200.0, len(reqs)))
+    srv.shutdown()
+    alone = serve.Server(serve.GpuExecutor(), slots=1, memory_budget=64 << 30)
+    for q, r in zip(reqs, res):
+        a = alone.submit(q).result()
+        assert a.cost == r.cost and np.array_equal(a.grad, r.grad)
+        if q.kind == "hvp":
+            assert np.array_equal(a.hvp, r.hvp)
+    alone.shutdown()
+    rep = serve.latency_report(res, t0, t1)
+    print("served:", rep)
+    assert rep["requests"] == 16
