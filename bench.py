@@ -66,20 +66,22 @@ def serving(n_req, seed):
     reqs = [serve.random_request(rng, n_range=(10, 20), L_range=(4, 16), ns_range=(16, 128))
             for _ in range(n_req)]
     # warm-up (first launches, allocator)
-    w = serve.Server(serve.GpuExecutor(), slots=1)
+    budget = 96 << 30
+    w = serve.Server(serve.GpuExecutor(), slots=1, memory_budget=budget)
     w.submit(reqs[0]).result()
     w.shutdown()
     # serial capacity: all requests queued at once, one slot
-    srv = serve.Server(serve.GpuExecutor(), slots=1)
+    srv = serve.Server(serve.GpuExecutor(), slots=1, memory_budget=budget)
     res, t0, t1 = serve.replay(srv, reqs, np.zeros(n_req))
     srv.shutdown()
     mu = n_req / (t1 - t0)
     lam = 0.9 * mu
     arrivals = serve.poisson_arrivals(rng, lam, n_req)
     out = {"requests": n_req, "n": [10, 20], "L": [4, 16], "N_s": [16, 128], "precision": "c64",
+           "memory_budget_GiB": budget >> 30, "slots": 4,
            "serial_capacity_rps": round(mu, 3), "arrival_rate_rps": round(lam, 3)}
     for name, slots in (("serial", 1), ("batched", 4)):
-        srv = serve.Server(serve.GpuExecutor(), slots=slots)
+        srv = serve.Server(serve.GpuExecutor(), slots=slots, memory_budget=budget)
         res, t0, t1 = serve.replay(srv, reqs, arrivals)
         srv.shutdown()
         rep = serve.latency_report(res, t0, t1)

@@ -75,6 +75,8 @@ class Problem:
     samples     : (N_s, n, 2) single-qubit states of the product-state samples.
     precision   : "c128" or "c64" (complex64 states, FP64 accumulation).
     ckpt_every  : layer-checkpoint interval (0 = keep every pass boundary).
+    workspace   : "torch" (allocate with torch), a (device pointer, bytes) block owned by the
+                  caller, or None (the library allocates).
     """
 
     def __init__(self, n, L, uref, samples, L_ref=None, precision="c128", ckpt_every=1,
@@ -101,9 +103,13 @@ class Problem:
             raise ValueError("invalid problem shape")
         self._ws = None
         ws_ptr = None
-        if workspace == "torch":
+        if isinstance(workspace, str) and workspace == "torch":
             self._ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=f"cuda:{device}")
             ws_ptr = C.c_void_p(self._ws.data_ptr())
+        elif isinstance(workspace, tuple):           # (device pointer, bytes) owned by the caller
+            if workspace[1] < self.ws_bytes:
+                raise MemoryError(f"workspace block of {workspace[1]} bytes, need {self.ws_bytes}")
+            ws_ptr = C.c_void_p(int(workspace[0]))
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         h = C.c_void_p()
         check(lib.qhvp_problem_create(self.ctx.handle, n, L, L_ref, dptr(_f64(uref)), dptr(_f64(samples)),

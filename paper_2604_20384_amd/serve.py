@@ -90,11 +90,61 @@ def plan_request(req: Request, bytes_fn, cap: int) -> Plan:
         chunks *= 2
 
 
+class Arena:
+    """First-fit allocator over one device buffer that is allocated once (from torch, so its HBM
+    shows in torch's statistics).  Blocks are 256-byte aligned offsets; not thread-safe (the
+    server calls it under its lock)."""
+
+    ALIGN = 256
+
+    def __init__(self, nbytes: int, device: int = 0, base_ptr: int | None = None):
+        self.size = nbytes
+        self.buf = None
+        if base_ptr is None:
+            import torch
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{device}")
+            base_ptr = self.buf.data_ptr()
+        self.base = base_ptr
+        self.free_list = [(0, nbytes)]          # sorted, coalesced (offset, size)
+        self.used = {}
+
+    def alloc(self, nbytes: int):
+        need = (nbytes + self.ALIGN - 1) // self.ALIGN * self.ALIGN
+        for i, (off, sz) in enumerate(self.free_list):
+            if sz >= need:
+                if sz == need:
+                    self.free_list.pop(i)
+                else:
+                    self.free_list[i] = (off + need, sz - need)
+                self.used[off] = need
+                return off
+        return None
+
+    def free(self, off: int):
+        need = self.used.pop(off)
+        self.free_list.append((off, need))
+        self.free_list.sort()
+        merged = []
+        for o, z in self.free_list:
+            if merged and merged[-1][0] + merged[-1][1] == o:
+                merged[-1] = (merged[-1][0], merged[-1][1] + z)
+            else:
+                merged.append((o, z))
+        self.free_list = merged
+
+    def largest_free(self) -> int:
+        return max((z for _, z in self.free_list), default=0)
+
+
 class GpuExecutor:
-    """Runs requests through the HIP library (paper_2604_20384_amd.api)."""
+    """Runs requests through the HIP library (paper_2604_20384_amd.api), each in a block of the
+    server's device arena."""
 
     def __init__(self, device: int = 0):
         self.device = device
+
+    def make_arena(self, nbytes: int) -> Arena:
+        return Arena(nbytes, self.device)
 
     def bytes_fn(self, n, L, L_ref, ns, precision, ckpt, tangent):
         from .api import workspace_bytes
@@ -104,15 +154,17 @@ class GpuExecutor:
         import torch
         return torch.cuda.Stream(device=self.device)
 
-    def run_chunk(self, req: Request, lo: int, hi: int, ckpt: int, stream):
-        """Returns (fidelity, grad, hvp) averaged over samples lo..hi-1."""
+    def run_chunk(self, req: Request, lo: int, hi: int, ckpt: int, stream, workspace=None):
+        """Returns (fidelity, grad, hvp) averaged over samples lo..hi-1; `workspace` is a
+        (device pointer, bytes) block."""
         import torch
 
         from .api import Problem
         Lr = req.L_ref if req.L_ref is not None else 2 * req.L
         with torch.cuda.stream(stream):
             p = Problem(req.n, req.L, req.uref, req.samples[lo:hi], L_ref=Lr, precision=req.precision,
-                        ckpt_every=ckpt, with_tangent=req.kind == "hvp", device=self.device, stream=stream)
+                        ckpt_every=ckpt, with_tangent=req.kind == "hvp", device=self.device, stream=stream,
+                        workspace=workspace if workspace is not None else "torch")
             try:
                 if req.kind == "hvp":
                     c, g, h = p.hvp(req.G, req.V)
@@ -134,6 +186,7 @@ class Server:
         self._q = collections.deque()
         self._cv = threading.Condition()
         self._free = memory_budget
+        self.arena = executor.make_arena(memory_budget) if hasattr(executor, "make_arena") else None
         self._stop = False
         self._next_id = 0
         self.results: list[Result] = []
@@ -161,15 +214,23 @@ class Server:
             while True:
                 if self._stop and not self._q:
                     return None
-                if self._q and self._q[0][1].bytes <= self._free:
-                    item = self._q.popleft()
-                    self._free -= item[1].bytes
-                    return item
+                if self._q:
+                    nbytes = self._q[0][1].bytes
+                    if self.arena is not None:
+                        off = self.arena.alloc(nbytes)
+                        if off is not None:
+                            return self._q.popleft() + (off,)
+                    elif nbytes <= self._free:
+                        self._free -= nbytes
+                        return self._q.popleft() + (None,)
                 self._cv.wait(0.05)
 
-    def _release(self, nbytes):
+    def _release(self, nbytes, off):
         with self._cv:
-            self._free += nbytes
+            if off is not None:
+                self.arena.free(off)
+            else:
+                self._free += nbytes
             self._cv.notify_all()
 
     def _worker(self, slot: int):
@@ -178,7 +239,8 @@ class Server:
             item = self._take()
             if item is None:
                 return
-            req, plan, fut = item
+            req, plan, fut, off = item
+            ws = None if off is None else (self.arena.base + off, plan.bytes)
             t0 = time.perf_counter()
             try:
                 F = 0.0
@@ -186,7 +248,10 @@ class Server:
                 h = np.zeros_like(req.G, dtype=np.complex128) if req.kind == "hvp" else None
                 ns = req.n_samples
                 for lo, hi in plan.chunks:
-                    f_c, g_c, h_c = self.ex.run_chunk(req, lo, hi, plan.ckpt_every, stream)
+                    if ws is None:
+                        f_c, g_c, h_c = self.ex.run_chunk(req, lo, hi, plan.ckpt_every, stream)
+                    else:
+                        f_c, g_c, h_c = self.ex.run_chunk(req, lo, hi, plan.ckpt_every, stream, workspace=ws)
                     w = (hi - lo) / ns
                     F += w * f_c
                     g += w * g_c
@@ -201,7 +266,7 @@ class Server:
             except BaseException as e:  # the request fails, the server keeps going
                 fut.set_exception(e)
             finally:
-                self._release(plan.bytes)
+                self._release(plan.bytes, off)
 
     def shutdown(self, wait: bool = True):
         with self._cv:
@@ -210,6 +275,7 @@ class Server:
         if wait:
             for t in self._threads:
                 t.join()
+            self.arena = None          # release the device buffer
 
 
 def latency_report(results, t_start: float, t_end: float) -> dict:

@@ -152,3 +152,17 @@ def test_gpu_results_alone_equal_results_in_the_mix(gpu):
     rep = serve.latency_report(res, t0, t1)
     print("served:", rep)
     assert rep["requests"] == 16
+
+
+def test_arena_first_fit_and_coalescing():
+    a = serve.Arena(4096, base_ptr=1 << 20)
+    x = a.alloc(1000)
+    y = a.alloc(1000)
+    z = a.alloc(1000)
+    assert (x, y, z) == (0, 1024, 2048) and a.alloc(2000) is None
+    a.free(y)
+    assert a.alloc(1100) is None and a.alloc(900) == 1024
+    a.free(1024)
+    a.free(x)
+    a.free(z)
+    assert a.free_list == [(0, 4096)] and a.largest_free() == 4096
