@@ -30,10 +30,13 @@ def parse():
     ap.add_argument("--L", type=int, default=20)
     ap.add_argument("--ns", type=int, default=256)
     ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--ckpt", type=int, default=1, help="layer checkpoint interval (0: every pass boundary)")
+    ap.add_argument("--ckpt", type=int, default=None,
+                    help="layer checkpoint interval (0: every pass boundary; default: the fastest that fits)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a 2 GiB device copy 5 times (calibrates HBM traffic counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=40)
+    ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--seed", type=int, default=1)
     return ap.parse_args()
 
@@ -89,12 +92,38 @@ def serving(n_req, seed):
     return out
 
 
+def copy_probe():
+    import torch
+    nbytes = 2 << 30
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "copies": 5}))
+
+
+def pick_ckpt(n, L, L_ref, ns, precision):
+    """Fastest checkpoint policy whose workspace fits the free HBM (8 GiB kept back)."""
+    import torch
+
+    from paper_2604_20384_amd.api import workspace_bytes
+    free, _ = torch.cuda.mem_get_info()
+    for ck in (0, -2, 1, 2, 4, 8):
+        if workspace_bytes(n, L, L_ref, ns, precision, ck, True) <= free - (8 << 30):
+            return ck
+    return 8
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import numpy as np
     import torch
@@ -105,6 +134,8 @@ def main():
     n, L, ns = args.n, args.L, args.ns
     K = num_gates(n, L)
     prob = make_problem(n, L, ns, seed=args.seed)
+    if args.ckpt is None:
+        args.ckpt = pick_ckpt(n, L, prob.L_ref, ns, args.precision)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     gp = Problem(n, L, prob.uref, prob.samples, L_ref=prob.L_ref, precision=args.precision,
