@@ -92,6 +92,23 @@ def serving(n_req, seed):
     return out
 
 
+def measured_traffic(kernel_name):
+    """HBM bytes per launch of `kernel_name` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (scaled by the copy-kernel calibration), or None if the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_k_bwd_c64.json")
+    src = os.path.join(ROOT, "paper_2604_20384_amd", "csrc", "qhvp_kernels.hip")
+    try:
+        rec = json.load(open(path))
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel") != kernel_name or not sha.startswith(rec["kernel_source_sha256_prefix"]):
+        return None
+    return (rec["fetch_kib_per_launch"] * rec["fetch_factor"] + rec["write_kib_per_launch"] * rec["write_factor"]) * 1024
+
+
 def copy_probe():
     import torch
     nbytes = 2 << 30
@@ -175,8 +192,10 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": VALU_PEAK_TFS, "unit": "TFLOP/s",
                 "frac": round(frac_alu, 4)}
-    roof.update({"traffic": None, "kernel": f"k_bwd<{'float' if args.precision == 'c64' else 'double'},true>"
-                 if dom == "backward" else f"k_fwd<{'float' if args.precision == 'c64' else 'double'},true>",
+    kname = (f"k_bwd<{'float' if args.precision == 'c64' else 'double'},true>" if dom == "backward"
+             else f"k_fwd<{'float' if args.precision == 'c64' else 'double'},true>")
+    traffic = measured_traffic(kname) if (n, L, ns) == (20, 20, 256) else None
+    roof.update({"traffic": traffic, "kernel": kname,
                  "avg_launch_ms": round(avg_ms, 4), "launches": st["launches"],
                  "alg_bytes_per_launch": bytes_per_launch, "alg_flops_per_launch": flops_per_launch,
                  "hbm_frac": round(frac_hbm, 4), "alu_frac": round(frac_alu, 4)})
