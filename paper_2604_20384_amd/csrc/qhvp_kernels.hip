@@ -256,6 +256,19 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   const long long it0 = items * blockIdx.x / gridDim.x;
   const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
 
+  // the next tile's loads are in flight while the current tile is computed
+  typename IO::V pf[2][IO::NV];
+  auto prefetch = [&](long long itn) {
+    const int sn = (int)(itn / tiles);
+    const long long bn = (long long)sn * dim + deposit(itn - (long long)sn * tiles, pd.ibit, n - mb);
+#pragma unroll
+    for (int v = 0; v < IO::NV; ++v) {
+      pf[0][v] = *(const typename IO::V*)(srcP + bn + xv[v]);
+      if (TANG) pf[1][v] = *(const typename IO::V*)(srcD + bn + xv[v]);
+    }
+  };
+  if (!gen && it0 < it1) prefetch(it0);
+
   for (long long it = it0; it < it1; ++it) {
     const int s = (int)(it / tiles);
     const int w = (int)(it - (long long)s * tiles);
@@ -275,10 +288,15 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
           }
         }
     } else {
-      IO::load(sP, srcP, base, xv, TS, tid);
-      if (TANG) IO::load(sD, srcD, base, xv, TS, tid);
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v) {
+        const int sl = IO::slot(IO::elem(tid, v), TS);
+        *(typename IO::V*)(sP + sl) = pf[0][v];
+        if (TANG) *(typename IO::V*)(sD + sl) = pf[1][v];
+      }
     }
     __syncthreads();
+    if (!gen && it + 1 < it1) prefetch(it + 1);
 
     for (int j = 0; j < ng; ++j) {
       const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
@@ -371,6 +389,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   __shared__ __attribute__((aligned(16))) T sY[NST * TSP];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sM[16 * 16];
+  // complex64: FP64 running sums of the per-tile FP32 MFMA accumulators, one column per thread
+  constexpr bool kF32 = std::is_same<R, float>::value;
+  __shared__ double sAcc[kF32 ? kMaxGates * 4 * kThreads : 1];
 
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
@@ -404,11 +425,13 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSP + cri;  // in units of R
 
   acc_t acc[kMaxGates];
-  double accd[kMaxGates][4];
 #pragma unroll
   for (int j = 0; j < kMaxGates; ++j) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) { acc[j][r] = 0; accd[j][r] = 0; }
+    for (int r = 0; r < 4; ++r) acc[j][r] = 0;
+  }
+  if constexpr (kF32) {
+    for (int i = tid; i < kMaxGates * 4 * kThreads; i += kThreads) sAcc[i] = 0;
   }
   // Groups g >= ngroups (only when mb < kMaxTileBits) map to tile indices >= 2^mb, which no tile
   // operation writes: zero them once so that their MFMA operands are zero.
@@ -421,29 +444,37 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   const long long it0 = items * blockIdx.x / gridDim.x;
   const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
 
+  // Common case (all four states come from memory): the next tile's loads are issued right
+  // after the current tile is in LDS, so they are in flight during the current tile's compute.
+  const bool common = !a.fold && !gen;
+  typename IO::V pf[4][IO::NV];
+  auto prefetch = [&](long long itn) {
+    const int sn = (int)(itn / tiles);
+    const long long bn = (long long)sn * dim + deposit(itn - (long long)sn * tiles, pd.ibit, n - mb);
+#pragma unroll
+    for (int v = 0; v < IO::NV; ++v) {
+      pf[0][v] = *(const typename IO::V*)(abA + bn + xv[v]);
+      if (TANG) pf[1][v] = *(const typename IO::V*)(abB + bn + xv[v]);
+      pf[2][v] = *(const typename IO::V*)(srcP + bn + xv[v]);
+      if (TANG) pf[3][v] = *(const typename IO::V*)(srcD + bn + xv[v]);
+    }
+  };
+  if (common && it0 < it1) prefetch(it0);
+
   for (long long it = it0; it < it1; ++it) {
     const int s = (int)(it / tiles);
     const int w = (int)(it - (long long)s * tiles);
     const long long sbase = (long long)s * dim;
     const long long base = sbase + deposit(w, pd.ibit, n - mb);
 
-    if (!a.fold && !gen) {
-      // common case: all four states come from memory; put every load in flight before any write
-      typename IO::V r[4][IO::NV];
-#pragma unroll
-      for (int v = 0; v < IO::NV; ++v) {
-        r[0][v] = *(const typename IO::V*)(abA + base + xv[v]);
-        if (TANG) r[1][v] = *(const typename IO::V*)(abB + base + xv[v]);
-        r[2][v] = *(const typename IO::V*)(srcP + base + xv[v]);
-        if (TANG) r[3][v] = *(const typename IO::V*)(srcD + base + xv[v]);
-      }
+    if (common) {
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v) {
         const int sl = IO::slot(IO::elem(tid, v), TS);
-        *(typename IO::V*)(sY + sl) = r[0][v];
-        if (TANG) *(typename IO::V*)(sY + TSP + sl) = r[1][v];
-        *(typename IO::V*)(sX + sl) = r[2][v];
-        if (TANG) *(typename IO::V*)(sX + TSP + sl) = r[3][v];
+        *(typename IO::V*)(sY + sl) = pf[0][v];
+        if (TANG) *(typename IO::V*)(sY + TSP + sl) = pf[1][v];
+        *(typename IO::V*)(sX + sl) = pf[2][v];
+        if (TANG) *(typename IO::V*)(sX + TSP + sl) = pf[3][v];
       }
     } else {
     // ---- backward states (a, b) at the pass output
@@ -488,6 +519,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     }
     }
     __syncthreads();
+    if (common && it + 1 < it1) prefetch(it + 1);
 
     // ---- forward recompute inside the tile; keep this lane's MFMA B operands of every gate
     R bop[kMaxGates][16];
@@ -560,12 +592,17 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       }
     }
 
-    // ---- complex64: one tile's FP32 partial sums into the FP64 accumulators
-    if constexpr (std::is_same<R, float>::value) {
+    // ---- complex64: one tile's FP32 partial sums into the FP64 accumulators (LDS, own column)
+    if constexpr (kF32) {
 #pragma unroll
       for (int j = 0; j < kMaxGates; ++j) {
+        if (j < ng) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) { accd[j][r] += (double)acc[j][r]; acc[j][r] = 0; }
+          for (int r = 0; r < 4; ++r) {
+            sAcc[(j * 4 + r) * kThreads + tid] += (double)acc[j][r];
+            acc[j][r] = 0;
+          }
+        }
       }
     }
 
@@ -576,21 +613,14 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     __syncthreads();
   }
 
-  if constexpr (std::is_same<R, double>::value) {
-#pragma unroll
-    for (int j = 0; j < kMaxGates; ++j) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) accd[j][r] = acc[j][r];
-    }
-  }
-
   // ---- per-workgroup environment partials: sum the 4 waves' 16x16 blocks, then combine
   double* sRed = (double*)sY;   // kThreads * 4 doubles fit in sY for both precisions
 #pragma unroll
   for (int j = 0; j < kMaxGates; ++j) {
     if (j < ng) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) sRed[(wave * 64 + lane) * 4 + r] = accd[j][r];
+      for (int r = 0; r < 4; ++r)
+        sRed[(wave * 64 + lane) * 4 + r] = kF32 ? sAcc[(j * 4 + r) * kThreads + tid] : (double)acc[j][r];
       __syncthreads();
       if (wave == 0) {
 #pragma unroll
