@@ -106,7 +106,9 @@ __device__ __forceinline__ void apply_w(const T* G, const T* V, T (&p)[4], T (&d
     }
   }
   if (TANG) {
-    asm volatile("" ::: "memory");
+    // V's scalar loads may not start before the G phase is done (bounds live scalar registers);
+    // a register-only dependency, so no wait on outstanding memory operations is implied
+    asm volatile("" : "+s"(V) : "v"(np[3].y));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -132,7 +134,7 @@ __device__ __forceinline__ void apply_wdag(const T* G, const T* V, T (&a)[4], T 
     }
   }
   if (TANG) {
-    asm volatile("" ::: "memory");
+    asm volatile("" : "+s"(V) : "v"(na[3].y));
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -166,8 +168,11 @@ template <typename T> struct Lds {
 // fewer than 2^kMaxTileBits elements alias to in-tile elements (deposit ignores bits >= mb), so
 // every address is in bounds and all loads can be in flight together; only the LDS writes and
 // global stores of such indices are skipped.
+typedef float qv4f __attribute__((ext_vector_type(4)));
+typedef double qv2d __attribute__((ext_vector_type(2)));
+
 template <typename T> struct TileIO {
-  using V = typename std::conditional<sizeof(T) == 8, float4, double2>::type;
+  using V = typename std::conditional<sizeof(T) == 8, qv4f, qv2d>::type;   // 16 bytes
   static constexpr int EPV = 16 / (int)sizeof(T);
   static constexpr int NV = (1 << kMaxTileBits) / EPV / kThreads;
   static __device__ __forceinline__ int elem(int tid, int v) { return EPV * (tid + kThreads * v); }
@@ -190,8 +195,8 @@ template <typename T> struct TileIO {
   }
   static __device__ __forceinline__ T part(const V& r, int e) {
     T o;
-    if constexpr (sizeof(T) == 8) { o.x = e ? r.z : r.x; o.y = e ? r.w : r.y; }
-    else { o.x = r.x; o.y = r.y; }
+    if constexpr (sizeof(T) == 8) { o.x = e ? r[2] : r[0]; o.y = e ? r[3] : r[1]; }
+    else { o.x = r[0]; o.y = r[1]; }
     return o;
   }
 };
@@ -257,17 +262,18 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
 
   // the next tile's loads are in flight while the current tile is computed
-  typename IO::V pf[2][IO::NV];
-  auto prefetch = [&](long long itn) {
-    const int sn = (int)(itn / tiles);
-    const long long bn = (long long)sn * dim + deposit(itn - (long long)sn * tiles, pd.ibit, n - mb);
-#pragma unroll
-    for (int v = 0; v < IO::NV; ++v) {
-      pf[0][v] = *(const typename IO::V*)(srcP + bn + xv[v]);
-      if (TANG) pf[1][v] = *(const typename IO::V*)(srcD + bn + xv[v]);
-    }
-  };
-  if (!gen && it0 < it1) prefetch(it0);
+  typename IO::V pf0[IO::NV], pf1[IO::NV];
+#define QHVP_FWD_PREFETCH(ITN)                                                                      \
+  {                                                                                                 \
+    const long long itn_ = (ITN);                                                                   \
+    const int sn_ = (int)(itn_ / tiles);                                                            \
+    const long long bn_ = (long long)sn_ * dim + deposit(itn_ - (long long)sn_ * tiles, pd.ibit, n - mb); \
+    _Pragma("unroll") for (int v = 0; v < IO::NV; ++v) {                                            \
+      pf0[v] = *(const typename IO::V*)(srcP + bn_ + xv[v]);                                        \
+      if (TANG) pf1[v] = *(const typename IO::V*)(srcD + bn_ + xv[v]);                              \
+    }                                                                                               \
+  }
+  if (!gen && it0 < it1) QHVP_FWD_PREFETCH(it0);
 
   for (long long it = it0; it < it1; ++it) {
     const int s = (int)(it / tiles);
@@ -291,12 +297,12 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v) {
         const int sl = IO::slot(IO::elem(tid, v), TS);
-        *(typename IO::V*)(sP + sl) = pf[0][v];
-        if (TANG) *(typename IO::V*)(sD + sl) = pf[1][v];
+        *(typename IO::V*)(sP + sl) = pf0[v];
+        if (TANG) *(typename IO::V*)(sD + sl) = pf1[v];
       }
     }
     __syncthreads();
-    if (!gen && it + 1 < it1) prefetch(it + 1);
+    if (!gen && it + 1 < it1) QHVP_FWD_PREFETCH(it + 1);
 
     for (int j = 0; j < ng; ++j) {
       const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
@@ -447,19 +453,20 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   // Common case (all four states come from memory): the next tile's loads are issued right
   // after the current tile is in LDS, so they are in flight during the current tile's compute.
   const bool common = !a.fold && !gen;
-  typename IO::V pf[4][IO::NV];
-  auto prefetch = [&](long long itn) {
-    const int sn = (int)(itn / tiles);
-    const long long bn = (long long)sn * dim + deposit(itn - (long long)sn * tiles, pd.ibit, n - mb);
-#pragma unroll
-    for (int v = 0; v < IO::NV; ++v) {
-      pf[0][v] = *(const typename IO::V*)(abA + bn + xv[v]);
-      if (TANG) pf[1][v] = *(const typename IO::V*)(abB + bn + xv[v]);
-      pf[2][v] = *(const typename IO::V*)(srcP + bn + xv[v]);
-      if (TANG) pf[3][v] = *(const typename IO::V*)(srcD + bn + xv[v]);
-    }
-  };
-  if (common && it0 < it1) prefetch(it0);
+  typename IO::V pfa[IO::NV], pfb[IO::NV], pfp[IO::NV], pfd[IO::NV];
+#define QHVP_BWD_PREFETCH(ITN)                                                                      \
+  {                                                                                                 \
+    const long long itn_ = (ITN);                                                                   \
+    const int sn_ = (int)(itn_ / tiles);                                                            \
+    const long long bn_ = (long long)sn_ * dim + deposit(itn_ - (long long)sn_ * tiles, pd.ibit, n - mb); \
+    _Pragma("unroll") for (int v = 0; v < IO::NV; ++v) {                                            \
+      pfa[v] = *(const typename IO::V*)(abA + bn_ + xv[v]);                                         \
+      if (TANG) pfb[v] = *(const typename IO::V*)(abB + bn_ + xv[v]);                               \
+      pfp[v] = *(const typename IO::V*)(srcP + bn_ + xv[v]);                                        \
+      if (TANG) pfd[v] = *(const typename IO::V*)(srcD + bn_ + xv[v]);                              \
+    }                                                                                               \
+  }
+  if (common && it0 < it1) QHVP_BWD_PREFETCH(it0);
 
   for (long long it = it0; it < it1; ++it) {
     const int s = (int)(it / tiles);
@@ -471,10 +478,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v) {
         const int sl = IO::slot(IO::elem(tid, v), TS);
-        *(typename IO::V*)(sY + sl) = pf[0][v];
-        if (TANG) *(typename IO::V*)(sY + TSP + sl) = pf[1][v];
-        *(typename IO::V*)(sX + sl) = pf[2][v];
-        if (TANG) *(typename IO::V*)(sX + TSP + sl) = pf[3][v];
+        *(typename IO::V*)(sY + sl) = pfa[v];
+        if (TANG) *(typename IO::V*)(sY + TSP + sl) = pfb[v];
+        *(typename IO::V*)(sX + sl) = pfp[v];
+        if (TANG) *(typename IO::V*)(sX + TSP + sl) = pfd[v];
       }
     } else {
     // ---- backward states (a, b) at the pass output
@@ -519,7 +526,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     }
     }
     __syncthreads();
-    if (common && it + 1 < it1) prefetch(it + 1);
+    if (common && it + 1 < it1) QHVP_BWD_PREFETCH(it + 1);
 
     // ---- forward recompute inside the tile; keep this lane's MFMA B operands of every gate
     R bop[kMaxGates][16];
@@ -655,6 +662,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     }
   }
 }
+
+#undef QHVP_FWD_PREFETCH
+#undef QHVP_BWD_PREFETCH
 
 // --------------------------------------------------------------------------------------------
 // Deterministic fixed-order reductions
