@@ -83,16 +83,27 @@ template <typename T> __device__ __forceinline__ T cmul(T a, T b) {
 
 // Uniform pointer to gate entries, made opaque to the optimiser so that the (scalar) loads of the
 // entries stay next to their use instead of being hoisted out of the tile loop into vector registers.
+template <typename R>
+using cptr = const __attribute__((address_space(4))) R*;   // constant address space: scalar loads
+
+// Gate entries as interleaved (re, im) scalars behind an opaque constant-address-space pointer.
 template <typename T>
-__device__ __forceinline__ const T* opaque(const T* p) {
+__device__ __forceinline__ cptr<decltype(T::x)> opaque(const T* p) {
   asm volatile("" : "+s"(p));
-  return p;
+  return (cptr<decltype(T::x)>)p;
+}
+template <typename T>
+__device__ __forceinline__ T centry(cptr<decltype(T::x)> m, int k) {
+  T r;
+  r.x = m[2 * k];
+  r.y = m[2 * k + 1];
+  return r;
 }
 
 // (p, d) <- (G p, G d + V p) on one 4-amplitude group (Eq. fis / Eq. dfis); the V terms come after a
 // compiler barrier so that only one matrix's scalar entries are live at a time.
 template <typename T, bool TANG>
-__device__ __forceinline__ void apply_w(const T* G, const T* V, T (&p)[4], T (&d)[4]) {
+__device__ __forceinline__ void apply_w(cptr<decltype(T::x)> G, cptr<decltype(T::x)> V, T (&p)[4], T (&d)[4]) {
   T np[4], nd[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -100,7 +111,7 @@ __device__ __forceinline__ void apply_w(const T* G, const T* V, T (&p)[4], T (&d
     nd[i] = cz<T>();
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const T g = G[4 * i + m];
+      const T g = centry<T>(G, 4 * i + m);
       np[i] = cfma(g, p[m], np[i]);
       if (TANG) nd[i] = cfma(g, d[m], nd[i]);
     }
@@ -112,7 +123,7 @@ __device__ __forceinline__ void apply_w(const T* G, const T* V, T (&p)[4], T (&d
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) nd[i] = cfma(V[4 * i + m], p[m], nd[i]);
+      for (int m = 0; m < 4; ++m) nd[i] = cfma(centry<T>(V, 4 * i + m), p[m], nd[i]);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) { p[i] = np[i]; if (TANG) d[i] = nd[i]; }
@@ -120,7 +131,7 @@ __device__ __forceinline__ void apply_w(const T* G, const T* V, T (&p)[4], T (&d
 
 // (a, b) <- (G^dag a, G^dag b + V^dag a) (Eq. bis / Eq. dbis), same phase split.
 template <typename T, bool TANG>
-__device__ __forceinline__ void apply_wdag(const T* G, const T* V, T (&a)[4], T (&b)[4]) {
+__device__ __forceinline__ void apply_wdag(cptr<decltype(T::x)> G, cptr<decltype(T::x)> V, T (&a)[4], T (&b)[4]) {
   T na[4], nb[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -128,7 +139,7 @@ __device__ __forceinline__ void apply_wdag(const T* G, const T* V, T (&a)[4], T 
     nb[i] = cz<T>();
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const T g = G[4 * m + i];          // (G^dag)_{im} = conj(G_{mi})
+      const T g = centry<T>(G, 4 * m + i);   // (G^dag)_{im} = conj(G_{mi})
       na[i] = cfmac(g, a[m], na[i]);
       if (TANG) nb[i] = cfmac(g, b[m], nb[i]);
     }
@@ -138,7 +149,7 @@ __device__ __forceinline__ void apply_wdag(const T* G, const T* V, T (&a)[4], T 
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) nb[i] = cfmac(V[4 * m + i], a[m], nb[i]);
+      for (int m = 0; m < 4; ++m) nb[i] = cfmac(centry<T>(V, 4 * m + i), a[m], nb[i]);
   }
 #pragma unroll
   for (int i = 0; i < 4; ++i) { a[i] = na[i]; if (TANG) b[i] = nb[i]; }
@@ -306,8 +317,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
 
     for (int j = 0; j < ng; ++j) {
       const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
-      const T* Gk = opaque(G + 16 * pd.gidx[j]);
-      const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
+      const auto Gk = opaque(G + 16 * pd.gidx[j]);
+      const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
       if (tid < ngroups) {
         const int t0 = ins0(ins0(tid, lo), hi);
         int ix[4];
@@ -546,8 +557,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           bop[j][c] = xs[2 * uo];
         }
         if (j + 1 < ng) {
-          const T* Gk = opaque(G + 16 * pd.gidx[j]);
-          const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
+          const auto Gk = opaque(G + 16 * pd.gidx[j]);
+          const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
           if (tid < ngroups) {
             const int t0 = ins0(ins0(tid, lo), hi);
             int ix[4];
@@ -580,8 +591,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
           acc[j] = M::step(ys[2 * uo], bop[j][c], acc[j]);
         }
-        const T* Gk = opaque(G + 16 * pd.gidx[j]);
-        const T* Vk = TANG ? opaque(V + 16 * pd.gidx[j]) : nullptr;
+        const auto Gk = opaque(G + 16 * pd.gidx[j]);
+        const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
         if (tid < ngroups) {
           const int t0 = ins0(ins0(tid, lo), hi);
           int ix[4];
