@@ -212,6 +212,14 @@ template <typename T> struct TileIO {
   }
 };
 
+// A register-only use of 16 values: the loads producing them are issued back to back and
+// waited for once, instead of one load-and-wait per use under register pressure.
+template <typename R>
+__device__ __forceinline__ void pin16(R (&v)[16]) {
+  asm volatile("" ::"v"(v[0]), "v"(v[1]), "v"(v[2]), "v"(v[3]), "v"(v[4]), "v"(v[5]), "v"(v[6]), "v"(v[7]),
+               "v"(v[8]), "v"(v[9]), "v"(v[10]), "v"(v[11]), "v"(v[12]), "v"(v[13]), "v"(v[14]), "v"(v[15]));
+}
+
 // insert a zero bit at position b
 __device__ __forceinline__ int ins0(int v, int b) { return ((v >> b) << (b + 1)) | (v & ((1 << b) - 1)); }
 
@@ -556,6 +564,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
           bop[j][c] = xs[2 * uo];
         }
+        pin16(bop[j]);
         if (j + 1 < ng) {
           const auto Gk = opaque(G + 16 * pd.gidx[j]);
           const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
@@ -586,11 +595,16 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
         const int p2 = LD::at(1 << grp_bit_pos(4, lo, hi)), p3 = LD::at(1 << grp_bit_pos(5, lo, hi));
         const int tl = LD::at(ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi));
         const R* ys = (const R*)sY + lane_scalar_off + 2 * tl;
+        // all 16 A operands in flight together (one wait), then the 16 accumulating MFMAs
+        R av[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
-          acc[j] = M::step(ys[2 * uo], bop[j][c], acc[j]);
+          av[c] = ys[2 * uo];
         }
+        pin16(av);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bop[j][c], acc[j]);
         const auto Gk = opaque(G + 16 * pd.gidx[j]);
         const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
         if (tid < ngroups) {
