@@ -137,6 +137,16 @@ qhvp_status qhvp_forward(qhvp_problem* p, const double* G, const double* V, qhvp
                          double* cost, double* fidelity);
 qhvp_status qhvp_backward(qhvp_problem* p, double* grad, double* hvp);
 
+/* Translationally invariant brickwalls (App. E, Alg. 3): every gate of layer l is the same
+ * G_(l).  G_layers, V_layers, grad_layers, hvp_layers hold L*16 complex (one 4x4 per layer).
+ * The gradient and HVP with respect to G_(l) are the sums over the layer's gates of the per-gate
+ * ones, with the direction V_(l) on every gate of layer l; Riemannian outputs are projected at
+ * G_(l) (App. F on U(4)^L, V projected first).  `grad_layers` may be NULL in qhvp_hvp_ti. */
+qhvp_status qhvp_grad_ti(qhvp_problem* p, const double* G_layers, qhvp_geometry geom, double* cost,
+                         double* grad_layers);
+qhvp_status qhvp_hvp_ti(qhvp_problem* p, const double* G_layers, const double* V_layers, qhvp_geometry geom,
+                        double* cost, double* grad_layers, double* hvp_layers);
+
 /* Per-sample overlaps T_s and Omega_s = D(T_s)[V] (n_samples complex each, host) of
  * the last cost/grad/hvp call (Omega is zero unless that call was an HVP). */
 qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega);

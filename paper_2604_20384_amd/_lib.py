@@ -51,6 +51,8 @@ _SIGS = {
     "qhvp_hvp": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp, _dp]),
     "qhvp_forward": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp]),
     "qhvp_backward": (C.c_int, [_vp, _dp, _dp]),
+    "qhvp_grad_ti": (C.c_int, [_vp, _dp, C.c_int, _dp, _dp]),
+    "qhvp_hvp_ti": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp, _dp]),
     "qhvp_overlaps": (C.c_int, [_vp, _dp, _dp]),
     "qhvp_problem_info": (C.c_int, [_vp, _ip, _ip, _szp, _ip]),
     "qhvp_last_device_ms": (C.c_double, [_vp]),

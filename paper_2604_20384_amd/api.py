@@ -170,6 +170,26 @@ class Problem:
         check(lib.qhvp_backward(self.handle, dptr(_f64(g)), None if h is None else dptr(_f64(h))))
         return g if h is None else (g, h)
 
+    # ---- translationally invariant circuits: one (4, 4) gate per layer
+    def grad_ti(self, G_layers, riemannian=False):
+        self.epoch += 1
+        G = _c128(G_layers, (self.L, 4, 4))
+        g = np.empty((self.L, 4, 4), dtype=np.complex128)
+        c = C.c_double()
+        check(lib.qhvp_grad_ti(self.handle, dptr(_f64(G)), int(riemannian), C.byref(c), dptr(_f64(g))))
+        return c.value, g
+
+    def hvp_ti(self, G_layers, V_layers, riemannian=False):
+        self.epoch += 1
+        G = _c128(G_layers, (self.L, 4, 4))
+        V = _c128(V_layers, (self.L, 4, 4))
+        g = np.empty((self.L, 4, 4), dtype=np.complex128)
+        h = np.empty((self.L, 4, 4), dtype=np.complex128)
+        c = C.c_double()
+        check(lib.qhvp_hvp_ti(self.handle, dptr(_f64(G)), dptr(_f64(V)), int(riemannian), C.byref(c),
+                              dptr(_f64(g)), dptr(_f64(h))))
+        return c.value, g, h
+
     def overlaps(self):
         T = np.empty(self.n_samples, dtype=np.complex128)
         O = np.empty(self.n_samples, dtype=np.complex128)

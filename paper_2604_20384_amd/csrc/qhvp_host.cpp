@@ -801,6 +801,73 @@ qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geo
   return qhvp_backward(p, grad, hvp);
 }
 
+// ---- translationally invariant circuits (App. E): one gate G_(l) per layer ----------------------
+
+namespace {
+// gate k of the brickwall belongs to layer layer_of[k]
+std::vector<int> gate_layers(int n, int L) {
+  std::vector<int> out;
+  for (int l = 0; l < L; ++l)
+    for (int q = l % 2; q + 1 < n; q += 2) out.push_back(l);
+  return out;
+}
+void ti_expand(const qhvp_problem* p, const double* layers, std::vector<double>& gates) {
+  const auto lay = gate_layers(p->n, p->L);
+  gates.resize((size_t)p->K * 32);
+  for (int k = 0; k < p->K; ++k) std::memcpy(&gates[(size_t)k * 32], layers + (size_t)lay[k] * 32, 32 * sizeof(double));
+}
+void ti_reduce(const qhvp_problem* p, const double* per_gate, double* layers) {
+  const auto lay = gate_layers(p->n, p->L);
+  std::memset(layers, 0, (size_t)p->L * 32 * sizeof(double));
+  for (int k = 0; k < p->K; ++k)
+    for (int e = 0; e < 32; ++e) layers[(size_t)lay[k] * 32 + e] += per_gate[(size_t)k * 32 + e];
+}
+}  // namespace
+
+qhvp_status qhvp_grad_ti(qhvp_problem* p, const double* G_layers, qhvp_geometry geom, double* cost,
+                         double* grad_layers) {
+  if (!p || !G_layers || !grad_layers) return fail(QHVP_ERR_INVALID, "bad arguments");
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  if (!finite_all(G_layers, (size_t)p->L * 32)) return fail(QHVP_ERR_INVALID, "G_layers has non-finite entries");
+  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->L, G_layers) > 1e-10)
+    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
+  std::vector<double> G, g((size_t)p->K * 32), gl((size_t)p->L * 32);
+  ti_expand(p, G_layers, G);
+  qhvp_status st = qhvp_grad(p, G.data(), QHVP_EUCLIDEAN, cost, g.data());
+  if (st) return st;
+  ti_reduce(p, g.data(), gl.data());
+  if (geom == QHVP_RIEMANNIAN) return qhvp_project(p->L, G_layers, gl.data(), grad_layers);
+  std::memcpy(grad_layers, gl.data(), gl.size() * sizeof(double));
+  return QHVP_OK;
+}
+
+qhvp_status qhvp_hvp_ti(qhvp_problem* p, const double* G_layers, const double* V_layers, qhvp_geometry geom,
+                        double* cost, double* grad_layers, double* hvp_layers) {
+  if (!p || !G_layers || !V_layers || !hvp_layers) return fail(QHVP_ERR_INVALID, "bad arguments");
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  if (!finite_all(G_layers, (size_t)p->L * 32) || !finite_all(V_layers, (size_t)p->L * 32))
+    return fail(QHVP_ERR_INVALID, "non-finite layer gates or directions");
+  std::vector<double> Vl(V_layers, V_layers + (size_t)p->L * 32);
+  if (geom == QHVP_RIEMANNIAN) {
+    if (qhvp_unitarity_error(p->L, G_layers) > 1e-10) return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
+    qhvp_project(p->L, G_layers, V_layers, Vl.data());   // tangent direction first (App. F)
+  }
+  std::vector<double> G, V, g((size_t)p->K * 32), h((size_t)p->K * 32), gl((size_t)p->L * 32), hl((size_t)p->L * 32);
+  ti_expand(p, G_layers, G);
+  ti_expand(p, Vl.data(), V);
+  qhvp_status st = qhvp_hvp(p, G.data(), V.data(), QHVP_EUCLIDEAN, cost, g.data(), h.data());
+  if (st) return st;
+  ti_reduce(p, g.data(), gl.data());
+  ti_reduce(p, h.data(), hl.data());
+  if (geom == QHVP_RIEMANNIAN) {
+    if (grad_layers) qhvp_project(p->L, G_layers, gl.data(), grad_layers);
+    return qhvp_riemannian_hvp(p->L, G_layers, gl.data(), hl.data(), Vl.data(), hvp_layers);
+  }
+  if (grad_layers) std::memcpy(grad_layers, gl.data(), gl.size() * sizeof(double));
+  std::memcpy(hvp_layers, hl.data(), hl.size() * sizeof(double));
+  return QHVP_OK;
+}
+
 qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
   if (p->last_T.empty()) return fail(QHVP_ERR_INVALID, "no evaluation yet");
