@@ -18,7 +18,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-VALU_PEAK_TFS = 78.6           # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FP32 non-packed = FP64 vector)
+# Compute peaks of the unit that executes the arithmetic of each precision: complex64 runs the gate
+# products and the environment sums on the FP32 matrix cores (dense MFMA FP32: 157.3 TFLOP/s);
+# complex128 runs the gate products on the FP64 vector ALU and the sums on FP64 MFMA, both 78.6.
+COMPUTE_PEAK = {"c64": ("mfma", 157.3), "c128": ("alu", 78.6)}
 
 
 def parse():
@@ -185,20 +188,22 @@ def main():
     flops_per_launch = st["flops"] / max(1, st["launches"])
     gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     tfs = flops_per_launch / (avg_ms * 1e-3) / 1e12
-    frac_hbm, frac_alu = gbs / HBM_PEAK_GBS, tfs / VALU_PEAK_TFS
-    if frac_hbm >= frac_alu:
+    unit_name, comp_peak = COMPUTE_PEAK[args.precision]
+    frac_hbm, frac_comp = gbs / HBM_PEAK_GBS, tfs / comp_peak
+    if frac_hbm >= frac_comp:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(frac_hbm, 4)}
     else:
-        roof = {"bound": "alu", "achieved": round(tfs, 2), "peak": VALU_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": round(frac_alu, 4)}
+        roof = {"bound": unit_name, "achieved": round(tfs, 2), "peak": comp_peak, "unit": "TFLOP/s",
+                "frac": round(frac_comp, 4)}
     kname = (f"k_bwd<{'float' if args.precision == 'c64' else 'double'},true>" if dom == "backward"
              else f"k_fwd<{'float' if args.precision == 'c64' else 'double'},true>")
     traffic = measured_traffic(kname) if (n, L, ns) == (20, 20, 256) else None
     roof.update({"traffic": traffic, "kernel": kname,
                  "avg_launch_ms": round(avg_ms, 4), "launches": st["launches"],
                  "alg_bytes_per_launch": bytes_per_launch, "alg_flops_per_launch": flops_per_launch,
-                 "hbm_frac": round(frac_hbm, 4), "alu_frac": round(frac_alu, 4)})
+                 "hbm_frac": round(frac_hbm, 4), "compute_frac": round(frac_comp, 4),
+                 "compute_peak_TFLOPs": comp_peak})
 
     out = {
         "metric": "HVPs/sec (n=20, L=20, N_s=256)",

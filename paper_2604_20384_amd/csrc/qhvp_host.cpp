@@ -113,6 +113,31 @@ std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* layer_f
   return passes;
 }
 
+// Padded LDS index of tile element t in the kernels' layout (16 spare bytes after every 256 bytes).
+int lds_at(int t, int elem_bytes) {
+  const int ps = elem_bytes == 8 ? 5 : 4;   // log2(elements per 256 bytes)
+  return t + (t >> ps) * (16 / elem_bytes);
+}
+
+// Per-pass constants of the kernels' tile addressing: the tile-enumeration mask and, per gate, the
+// padded LDS offsets of the group-index bits (zero bits inserted at tlo < thi) and of tlo / thi.
+void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
+  for (auto& pd : passes) {
+    pd.imask = 0;
+    for (int i = 0; i < pd.n - pd.mb; ++i) pd.imask |= 1ULL << pd.ibit[i];
+    for (int j = 0; j < pd.ng; ++j) {
+      const int lo = pd.tlo[j], hi = pd.thi[j];
+      for (int i = 0; i < 8; ++i) {
+        int pos = i + (i >= lo ? 1 : 0);
+        pos += (pos >= hi ? 1 : 0);
+        pd.goff[j][i] = lds_at(1 << pos, elem_bytes);
+      }
+      pd.aoff[j][0] = lds_at(1 << lo, elem_bytes);
+      pd.aoff[j][1] = lds_at(1 << hi, elem_bytes);
+    }
+  }
+}
+
 // Segments of the backward sweep (pass index ranges); each segment starts at a stored
 // checkpoint (pass 0's input is regenerated from the samples).
 std::vector<std::pair<int, int>> plan_segments(int n, int L, int ckpt_every) {
@@ -504,7 +529,7 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), b, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, bytes, pass_flops(p, b.pd, tangent, true)));
-      const int nwg = qhvp::grid_size((long long)p->Ns << (p->n - b.pd.mb));
+      const int nwg = qhvp::bwd_grid(p->dprec(), tangent, (long long)p->Ns << (p->n - b.pd.mb));
       HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_reduce_env(envpart, nwg, b.pd, env, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_REDUCE, (double)nwg * b.pd.ng * qhvp::kEnvVals * 8, 0));
@@ -661,6 +686,8 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
   p->stream = (hipStream_t)hip_stream;
   p->passes = plan_circuit(n, L, nullptr);
   p->ref_passes = plan_circuit(n, L_ref, nullptr);
+  fill_tile_offsets(p->passes, (int)p->amp());
+  fill_tile_offsets(p->ref_passes, (int)p->amp());
   p->seg = plan_segments(n, L, ckpt_every);
   p->lay = lay;
   p->last_ms = 0;

@@ -27,6 +27,12 @@ struct PassDesc {
   int thi[kMaxGates];           // tile bit of qubit q   (more significant bit of the pair)
   int abit[kMaxTileBits];       // statevector bit of each tile bit
   int ibit[kMaxQubits];         // statevector bits that index tiles, ascending
+  unsigned long long imask;     // OR of 1 << ibit[i]: tile w of a sample starts at pdep(w, imask)
+  // Padded LDS offsets (element units of the problem's precision) for gate slot j, filled by the
+  // host for the kernels' tile layout: a group index (the 8 tile bits other than tlo, thi) maps to
+  // the sum of goff[j][i] over its set bits i; tile bits tlo / thi add aoff[j][0] / aoff[j][1].
+  int goff[kMaxGates][8];
+  int aoff[kMaxGates][2];
 };
 
 enum Prec { P_C128 = 0, P_C64 = 1 };
@@ -66,7 +72,13 @@ struct BwdArgs {
   double* env_part;
 };
 
+// Upper bound of the workgroup count of any pass kernel over `items` tiles (sizes per-workgroup
+// buffers); fwd_grid / bwd_grid give the count actually launched on the current device (at most
+// the workgroups that are resident at once).
 int grid_size(long long items);
+int fwd_grid(Prec prec, int tangent, long long items);
+int bwd_grid(Prec prec, int tangent, long long items);
+
 
 // Launchers (return a hipError_t as int).
 int launch_fwd(Prec prec, const FwdArgs& a, void* stream);

@@ -223,12 +223,126 @@ __device__ __forceinline__ void pin16(R (&v)[16]) {
 // insert a zero bit at position b
 __device__ __forceinline__ int ins0(int v, int b) { return ((v >> b) << (b + 1)) | (v & ((1 << b) - 1)); }
 
+// --------------------------------------------------------------------------------------------
+// complex64 gate application on the matrix cores
+// --------------------------------------------------------------------------------------------
+// Per group (the 4 amplitudes of a qubit pair), W = [[X, 0], [Y, X]] acts on the 16 reals of
+// (p, d) as one real 16x16 matrix.  Its columns (inputs) are ordered 4*c + g and its rows
+// (outputs) 4*g + c, with g the amplitude of the pair (2*b_hi + b_lo) and c = 2*state + (0 re |
+// 1 im).  With 16 groups as the 16 columns of v_mfma_f32_16x16x4f32, MFMA step c consumes
+// component c of every amplitude, so lane (g = lane/16, col = lane%16) supplies amplitude g of
+// group col in all four steps and receives amplitude g of the result: state in, state out, same
+// lanes.  The A operand of lane l in step c is entry (l%16, 4c + l/16) of the real matrix, i.e.
+// one of +-Re, +-Im of a single complex entry u of X or Y, or 0:
+//   step 0: (Re x, Im x, Re y, Im y)[l%4]      step 1: (-Im x, Re x, -Im y, Re y)[l%4]
+//   step 2: (0, 0, Re x, Im x)[l%4]            step 3: (0, 0, -Im x, Re x)[l%4]
+// with x, y the entries [(l/4)%4][l/16] of X, Y (forward), or the conjugates of the entries
+// [l/16][(l/4)%4] (the form [[X^dag, 0], [Y^dag, X^dag]] of the backward recursion).
+__device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int e, bool conj_, int lane) {
+  float2 x = X[e], y = Y[e];
+  if (conj_) { x.y = -x.y; y.y = -y.y; }
+  const bool odd = (lane & 1) != 0, low = (lane & 2) == 0;
+  const float2 u = low ? x : y;
+  qv4f A;
+  A[0] = odd ? u.y : u.x;
+  A[1] = odd ? u.x : -u.y;
+  A[2] = low ? 0.f : (odd ? x.y : x.x);
+  A[3] = low ? 0.f : (odd ? x.x : -x.y);
+  return A;
+}
+
+// (p, d) <- W (p, d) on the 64 groups of one wave: four chains of 16 groups; all LDS reads first,
+// then the MFMAs, then the writes.  tl: this lane's LDS offset (amplitude g of group col, chain 0);
+// ch[c]: the wave-uniform offset of chain c.  Groups grp0 + 16c >= ngroups exist only in tiles of
+// fewer than 2^kMaxTileBits amplitudes; they read in-bounds LDS and are not written back.
+template <bool TANG>
+__device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* sD, int tl, const int (&ch)[4],
+                                             int grp0, int ngroups) {
+  float2 p[4], d[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    p[c] = sP[tl + ch[c]];
+    if (TANG) d[c] = sD[tl + ch[c]];
+  }
+  Mfma<float>::acc_t r[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    r[c][0] = 0; r[c][1] = 0; r[c][2] = 0; r[c][3] = 0;
+    r[c] = Mfma<float>::step(A[0], p[c].x, r[c]);
+    r[c] = Mfma<float>::step(A[1], p[c].y, r[c]);
+    if (TANG) {
+      r[c] = Mfma<float>::step(A[2], d[c].x, r[c]);
+      r[c] = Mfma<float>::step(A[3], d[c].y, r[c]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    if (grp0 + 16 * c < ngroups) {
+      sP[tl + ch[c]] = make_float2(r[c][0], r[c][1]);
+      if (TANG) sD[tl + ch[c]] = make_float2(r[c][2], r[c][3]);
+    }
+  }
+}
+
+__device__ __forceinline__ int bitsel(int v, int b, int off) { return ((v >> b) & 1) ? off : 0; }
+
+// Per-gate LDS offsets of a pass, staged in LDS once per workgroup (kOffs ints per gate slot:
+// goff[0..8), aoff[0..2)).  Read back after a barrier, they cannot be hoisted out of the tile loop
+// (where they would occupy, then spill, scalar registers); readfirstlane keeps them scalar.
+constexpr int kOffs = 10;
+__device__ __forceinline__ void stage_offsets(const PassDesc& pd, int* sOff, int tid) {
+  for (int j = 0; j < pd.ng; ++j) {
+    if (tid < 8) sOff[kOffs * j + tid] = pd.goff[j][tid];
+    else if (tid < 10) sOff[kOffs * j + tid] = pd.aoff[j][tid - 8];
+  }
+}
+struct GateOff {
+  int go[8], ao[2];
+};
+__device__ __forceinline__ GateOff gate_offsets(const int* sOff, int j) {
+  GateOff o;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o.go[i] = __builtin_amdgcn_readfirstlane(sOff[kOffs * j + i]);
+  o.ao[0] = __builtin_amdgcn_readfirstlane(sOff[kOffs * j + 8]);
+  o.ao[1] = __builtin_amdgcn_readfirstlane(sOff[kOffs * j + 9]);
+  return o;
+}
+
+// LDS offsets of gate slot j for the MFMA gate application of this lane / wave (group index
+// 64*wave + 16*c + col, amplitude g), from the pass constants goff / aoff.
+__device__ __forceinline__ void w_offsets(const GateOff& o, int wave, int lane, int& tl, int (&ch)[4]) {
+  const int* go = o.go;
+  const int* ao = o.ao;
+  const int col = lane & 15, g = lane >> 4;
+  tl = bitsel(col, 0, go[0]) + bitsel(col, 1, go[1]) + bitsel(col, 2, go[2]) + bitsel(col, 3, go[3]) +
+       bitsel(g, 0, ao[0]) + bitsel(g, 1, ao[1]);
+  const int wv = bitsel(wave, 0, go[6]) + bitsel(wave, 1, go[7]);
+  ch[0] = wv;
+  ch[1] = wv + go[4];
+  ch[2] = wv + go[5];
+  ch[3] = wv + go[4] + go[5];
+}
+
+// Stage the G (and V) entries of the pass's gates in LDS: sGV[32 j + e] = G_(gidx j)[e],
+// sGV[32 j + 16 + e] = V_(gidx j)[e] (0 without tangent).  Visible after the next barrier.
+template <bool TANG>
+__device__ __forceinline__ void stage_gates(const PassDesc& pd, const float2* G, const float2* V, float2* sGV, int tid) {
+  for (int j = 0; j < pd.ng; ++j) {
+    const int k = pd.gidx[j];
+    if (tid < 16) sGV[32 * j + tid] = G[16 * k + tid];
+    else if (tid < 32) sGV[32 * j + tid] = TANG ? V[16 * k + tid - 16] : make_float2(0.f, 0.f);
+  }
+}
+
 // Scatter the low `cnt` bits of v to the statevector bit positions pos[0..cnt).
 __device__ __forceinline__ long long deposit(long long v, const int* pos, int cnt) {
   long long x = 0;
   for (int i = 0; i < cnt; ++i) x |= ((v >> i) & 1LL) << pos[i];
   return x;
 }
+
+// Next tile offset in enumeration order: pdep(w + 1, mask) from x = pdep(w, mask); 0 after the last.
+__device__ __forceinline__ unsigned next_tile(unsigned x, unsigned mask) { return ((x | ~mask) + 1u) & mask; }
 
 // Product state amplitude at statevector index x: prod_q u_q[bit of qubit q] (Sec. IV, Haar product states).
 template <typename T>
@@ -250,13 +364,17 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   using T = typename CT<R>::T;
   using LD = Lds<T>;
   using IO = TileIO<T>;
+  constexpr bool kF32 = std::is_same<R, float>::value;
   __shared__ __attribute__((aligned(16))) T sP[LD::TSP];
   __shared__ __attribute__((aligned(16))) T sD[TANG ? LD::TSP : 1];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sRed[kThreads / 64][4];
+  __shared__ float2 sGV[kF32 ? kMaxGates * 32 : 1];
+  __shared__ int sOff[kMaxGates * kOffs];
 
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int n = pd.n, mb = pd.mb, ng = pd.ng;
   const int TS = 1 << mb, ngroups = TS >> 2;
   const long long dim = 1LL << n;
@@ -272,6 +390,11 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   const T* __restrict__ samp = (const T*)a.samples;
   const bool gen = (srcP == nullptr);
   const bool ovl = (a.ov_part != nullptr);
+  const unsigned imask = (unsigned)pd.imask;
+  const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);   // entry of X, Y behind this lane's operands
+
+  if constexpr (kF32) stage_gates<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
+  stage_offsets(pd, sOff, tid);
 
   int xv[IO::NV];
 #pragma unroll
@@ -279,26 +402,31 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
 
   const long long it0 = items * blockIdx.x / gridDim.x;
   const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
+  // current tile: sample s, offset x = pdep(tile index within the sample, imask)
+  int s = 0;
+  unsigned x = 0;
+  if (it0 < it1) {
+    s = (int)(it0 / tiles);
+    x = (unsigned)deposit(it0 - (long long)s * tiles, pd.ibit, n - mb);
+  }
 
   // the next tile's loads are in flight while the current tile is computed
   typename IO::V pf0[IO::NV], pf1[IO::NV];
-#define QHVP_FWD_PREFETCH(ITN)                                                                      \
+#define QHVP_FWD_PREFETCH(S, X)                                                                     \
   {                                                                                                 \
-    const long long itn_ = (ITN);                                                                   \
-    const int sn_ = (int)(itn_ / tiles);                                                            \
-    const long long bn_ = (long long)sn_ * dim + deposit(itn_ - (long long)sn_ * tiles, pd.ibit, n - mb); \
+    const long long bn_ = (long long)(S) * dim + (X);                                               \
     _Pragma("unroll") for (int v = 0; v < IO::NV; ++v) {                                            \
       pf0[v] = *(const typename IO::V*)(srcP + bn_ + xv[v]);                                        \
       if (TANG) pf1[v] = *(const typename IO::V*)(srcD + bn_ + xv[v]);                              \
     }                                                                                               \
   }
-  if (!gen && it0 < it1) QHVP_FWD_PREFETCH(it0);
+  if (!gen && it0 < it1) QHVP_FWD_PREFETCH(s, x);
 
   for (long long it = it0; it < it1; ++it) {
-    const int s = (int)(it / tiles);
-    const int w = (int)(it - (long long)s * tiles);
     const long long sbase = (long long)s * dim;
-    const long long base = sbase + deposit(w, pd.ibit, n - mb);
+    const long long base = sbase + x;
+    const unsigned xn = next_tile(x, imask);
+    const int sn = s + (xn == 0u ? 1 : 0);
     if (gen) {
       if (tid < 2 * n) sU[tid] = samp[(long long)s * 2 * n + tid];
       __syncthreads();
@@ -308,7 +436,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         for (int e = 0; e < IO::EPV; ++e) {
           const int t = IO::elem(tid, v) + e;
           if (t < TS) {
-            sP[LD::at(t)] = product_amp(sU, n, base - sbase + xv[v] + e);
+            sP[LD::at(t)] = product_amp(sU, n, (long long)x + xv[v] + e);
             if (TANG) sD[LD::at(t)] = cz<T>();
           }
         }
@@ -321,24 +449,31 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       }
     }
     __syncthreads();
-    if (!gen && it + 1 < it1) QHVP_FWD_PREFETCH(it + 1);
+    if (!gen && it + 1 < it1) QHVP_FWD_PREFETCH(sn, xn);
 
     for (int j = 0; j < ng; ++j) {
-      const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
-      const auto Gk = opaque(G + 16 * pd.gidx[j]);
-      const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
-      if (tid < ngroups) {
-        const int t0 = ins0(ins0(tid, lo), hi);
-        int ix[4];
-        ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+      if constexpr (kF32) {
+        int tl, ch[4];
+        w_offsets(gate_offsets(sOff, j), wave, lane, tl, ch);
+        const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_fwd, false, lane);
+        apply_w_mfma<TANG>(A, sP, sD, tl, ch, 64 * wave + (lane & 15), ngroups);
+      } else {
+        const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
+        const auto Gk = opaque(G + 16 * pd.gidx[j]);
+        const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
+        if (tid < ngroups) {
+          const int t0 = ins0(ins0(tid, lo), hi);
+          int ix[4];
+          ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
-        T p[4], d[4];
+          for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
+          T p[4], d[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { p[i] = sP[ix[i]]; if (TANG) d[i] = sD[ix[i]]; }
-        apply_w<T, TANG>(Gk, Vk, p, d);
+          for (int i = 0; i < 4; ++i) { p[i] = sP[ix[i]]; if (TANG) d[i] = sD[ix[i]]; }
+          apply_w<T, TANG>(Gk, Vk, p, d);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) { sP[ix[i]] = p[i]; if (TANG) sD[ix[i]] = d[i]; }
+          for (int i = 0; i < 4; ++i) { sP[ix[i]] = p[i]; if (TANG) sD[ix[i]] = d[i]; }
+        }
       }
       __syncthreads();
     }
@@ -386,19 +521,14 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       if (TANG) IO::store(dstD, sD, base, xv, TS, tid);
     }
     __syncthreads();
+    s = sn;
+    x = xn;
   }
 }
 
 // --------------------------------------------------------------------------------------------
 // Backward pass with environment accumulation
 // --------------------------------------------------------------------------------------------
-
-// Position, after inserting zero bits at tile bits lo < hi, of group-index bit i.
-__device__ __forceinline__ int grp_bit_pos(int i, int lo, int hi) {
-  int p = i + (i >= lo ? 1 : 0);
-  return p + (p >= hi ? 1 : 0);
-}
-
 template <typename R, bool TANG>
 __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   using T = typename CT<R>::T;
@@ -408,6 +538,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   using IO = TileIO<T>;
   constexpr int TSMAX = LD::TSMAX, TSP = LD::TSP;
   constexpr int NST = TANG ? 2 : 1;
+  constexpr bool kF32 = std::is_same<R, float>::value;
   // sX: forward states (psi | dpsi), sY: backward states (a | b); element t of state st at
   // [st*TSP + LD::at(t)]
   __shared__ __attribute__((aligned(16))) T sX[NST * TSP];
@@ -415,12 +546,14 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sM[16 * 16];
   // complex64: FP64 running sums of the per-tile FP32 MFMA accumulators, one column per thread
-  constexpr bool kF32 = std::is_same<R, float>::value;
   __shared__ double sAcc[kF32 ? kMaxGates * 4 * kThreads : 1];
+  __shared__ float2 sGV[kF32 ? kMaxGates * 32 : 1];
+  __shared__ int sOff[kMaxGates * kOffs];
 
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
+  const int uwave = __builtin_amdgcn_readfirstlane(wave);
   const int n = pd.n, mb = pd.mb, ng = pd.ng;
   const int TS = 1 << mb, ngroups = TS >> 2;
   const long long dim = 1LL << n;
@@ -435,18 +568,24 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   const T* __restrict__ phi0 = (const T*)a.phi0;
   const T* __restrict__ samp = (const T*)a.samples;
   const bool gen = (srcP == nullptr);
+  const unsigned imask = (unsigned)pd.imask;
+  const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);
+  const int e_bwd = 4 * (lane >> 4) + ((lane >> 2) & 3);
+
+  if constexpr (kF32) stage_gates<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
+  stage_offsets(pd, sOff, tid);
 
   int xv[IO::NV];
 #pragma unroll
   for (int v = 0; v < IO::NV; ++v) xv[v] = (int)deposit(IO::elem(tid, v), pd.abit, mb);
 
-  // MFMA operand of this lane: real part cri of amplitude cidx (pair index 2*b_hi + b_lo) of state
-  // cst, for group wave*64 + 4*c + sub in chunk c (A: rows = lane%16, B: columns = lane%16).
+  // MFMA operand of this lane for the environment sums: real part cri of amplitude cidx (pair
+  // index 2*b_hi + b_lo) of state cst, for group 64*wave + 4*c + sub in chunk c (A: rows =
+  // lane%16, B: columns = lane%16).
   const int comp = lane & 15, sub = lane >> 4;
   const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
   // Without tangent states the b rows / dpsi columns only feed the unused D sums; those lanes read
   // the a / psi arrays (in bounds) and their products are discarded.
-  const int g_lane = wave * 64 + sub;                 // group of chunk 0
   const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSP + cri;  // in units of R
 
   acc_t acc[kMaxGates];
@@ -468,16 +607,20 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 
   const long long it0 = items * blockIdx.x / gridDim.x;
   const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
+  int s = 0;
+  unsigned x = 0;
+  if (it0 < it1) {
+    s = (int)(it0 / tiles);
+    x = (unsigned)deposit(it0 - (long long)s * tiles, pd.ibit, n - mb);
+  }
 
   // Common case (all four states come from memory): the next tile's loads are issued right
   // after the current tile is in LDS, so they are in flight during the current tile's compute.
   const bool common = !a.fold && !gen;
   typename IO::V pfa[IO::NV], pfb[IO::NV], pfp[IO::NV], pfd[IO::NV];
-#define QHVP_BWD_PREFETCH(ITN)                                                                      \
+#define QHVP_BWD_PREFETCH(S, X)                                                                     \
   {                                                                                                 \
-    const long long itn_ = (ITN);                                                                   \
-    const int sn_ = (int)(itn_ / tiles);                                                            \
-    const long long bn_ = (long long)sn_ * dim + deposit(itn_ - (long long)sn_ * tiles, pd.ibit, n - mb); \
+    const long long bn_ = (long long)(S) * dim + (X);                                               \
     _Pragma("unroll") for (int v = 0; v < IO::NV; ++v) {                                            \
       pfa[v] = *(const typename IO::V*)(abA + bn_ + xv[v]);                                         \
       if (TANG) pfb[v] = *(const typename IO::V*)(abB + bn_ + xv[v]);                               \
@@ -485,13 +628,13 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       if (TANG) pfd[v] = *(const typename IO::V*)(srcD + bn_ + xv[v]);                              \
     }                                                                                               \
   }
-  if (common && it0 < it1) QHVP_BWD_PREFETCH(it0);
+  if (common && it0 < it1) QHVP_BWD_PREFETCH(s, x);
 
   for (long long it = it0; it < it1; ++it) {
-    const int s = (int)(it / tiles);
-    const int w = (int)(it - (long long)s * tiles);
     const long long sbase = (long long)s * dim;
-    const long long base = sbase + deposit(w, pd.ibit, n - mb);
+    const long long base = sbase + x;
+    const unsigned xn = next_tile(x, imask);
+    const int sn = s + (xn == 0u ? 1 : 0);
 
     if (common) {
 #pragma unroll
@@ -535,7 +678,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
         for (int e = 0; e < IO::EPV; ++e) {
           const int t = IO::elem(tid, v) + e;
           if (t < TS) {
-            sX[LD::at(t)] = product_amp(sU, n, base - sbase + xv[v] + e);
+            sX[LD::at(t)] = product_amp(sU, n, (long long)x + xv[v] + e);
             if (TANG) sX[TSP + LD::at(t)] = cz<T>();
           }
         }
@@ -545,41 +688,50 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     }
     }
     __syncthreads();
-    if (common && it + 1 < it1) QHVP_BWD_PREFETCH(it + 1);
+    if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
 
     // ---- forward recompute inside the tile; keep this lane's MFMA B operands of every gate
     R bop[kMaxGates][16];
 #pragma unroll
     for (int j = 0; j < kMaxGates; ++j) {
       if (j < ng) {
-        const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
-        // padded element offset of chunk c = sum over the 4 bits of 4c of their (padded) inserted
-        // positions; wave-uniform, and disjoint in bits from this lane's part tl
-        const int p0 = LD::at(1 << grp_bit_pos(2, lo, hi)), p1 = LD::at(1 << grp_bit_pos(3, lo, hi));
-        const int p2 = LD::at(1 << grp_bit_pos(4, lo, hi)), p3 = LD::at(1 << grp_bit_pos(5, lo, hi));
-        const int tl = LD::at(ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi));
+        const GateOff O = gate_offsets(sOff, j);
+        const int* go = O.go;
+        const int* ao = O.ao;
+        // LDS offset of this lane's operand in chunk 0 (group bits 0, 1 = sub; 6, 7 = wave) and the
+        // wave-uniform offsets of the chunks (group bits 2..5)
+        const int tl = bitsel(sub, 0, go[0]) + bitsel(sub, 1, go[1]) + bitsel(cidx, 0, ao[0]) +
+                       bitsel(cidx, 1, ao[1]) + bitsel(uwave, 0, go[6]) + bitsel(uwave, 1, go[7]);
         const R* xs = (const R*)sX + lane_scalar_off + 2 * tl;
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
+          const int uo = ((c & 1) ? go[2] : 0) + ((c & 2) ? go[3] : 0) + ((c & 4) ? go[4] : 0) + ((c & 8) ? go[5] : 0);
           bop[j][c] = xs[2 * uo];
         }
         pin16(bop[j]);
         if (j + 1 < ng) {
-          const auto Gk = opaque(G + 16 * pd.gidx[j]);
-          const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
-          if (tid < ngroups) {
-            const int t0 = ins0(ins0(tid, lo), hi);
-            int ix[4];
-            ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+          if constexpr (kF32) {
+            int tw, ch[4];
+            w_offsets(O, uwave, lane, tw, ch);
+            const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_fwd, false, lane);
+            apply_w_mfma<TANG>(A, sX, sX + TSP, tw, ch, 64 * uwave + (lane & 15), ngroups);
+          } else {
+            const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
+            const auto Gk = opaque(G + 16 * pd.gidx[j]);
+            const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
+            if (tid < ngroups) {
+              const int t0 = ins0(ins0(tid, lo), hi);
+              int ix[4];
+              ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
-            T p[4], d[4];
+              for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
+              T p[4], d[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
-            apply_w<T, TANG>(Gk, Vk, p, d);
+              for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
+              apply_w<T, TANG>(Gk, Vk, p, d);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSP + ix[i]] = d[i]; }
+              for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSP + ix[i]] = d[i]; }
+            }
           }
           __syncthreads();
         }
@@ -590,35 +742,44 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
     for (int j = kMaxGates - 1; j >= 0; --j) {
       if (j < ng) {
-        const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
-        const int p0 = LD::at(1 << grp_bit_pos(2, lo, hi)), p1 = LD::at(1 << grp_bit_pos(3, lo, hi));
-        const int p2 = LD::at(1 << grp_bit_pos(4, lo, hi)), p3 = LD::at(1 << grp_bit_pos(5, lo, hi));
-        const int tl = LD::at(ins0(ins0(g_lane, lo), hi) | ((cidx & 1) << lo) | ((cidx >> 1) << hi));
+        const GateOff O = gate_offsets(sOff, j);
+        const int* go = O.go;
+        const int* ao = O.ao;
+        const int tl = bitsel(sub, 0, go[0]) + bitsel(sub, 1, go[1]) + bitsel(cidx, 0, ao[0]) +
+                       bitsel(cidx, 1, ao[1]) + bitsel(uwave, 0, go[6]) + bitsel(uwave, 1, go[7]);
         const R* ys = (const R*)sY + lane_scalar_off + 2 * tl;
         // all 16 A operands in flight together (one wait), then the 16 accumulating MFMAs
         R av[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
-          const int uo = ((c & 1) ? p0 : 0) + ((c & 2) ? p1 : 0) + ((c & 4) ? p2 : 0) + ((c & 8) ? p3 : 0);
+          const int uo = ((c & 1) ? go[2] : 0) + ((c & 2) ? go[3] : 0) + ((c & 4) ? go[4] : 0) + ((c & 8) ? go[5] : 0);
           av[c] = ys[2 * uo];
         }
         pin16(av);
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bop[j][c], acc[j]);
-        const auto Gk = opaque(G + 16 * pd.gidx[j]);
-        const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
-        if (tid < ngroups) {
-          const int t0 = ins0(ins0(tid, lo), hi);
-          int ix[4];
-          ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
+        if constexpr (kF32) {
+          int tw, ch[4];
+          w_offsets(O, uwave, lane, tw, ch);
+          const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_bwd, true, lane);
+          apply_w_mfma<TANG>(A, sY, sY + TSP, tw, ch, 64 * uwave + (lane & 15), ngroups);
+        } else {
+          const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
+          const auto Gk = opaque(G + 16 * pd.gidx[j]);
+          const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
+          if (tid < ngroups) {
+            const int t0 = ins0(ins0(tid, lo), hi);
+            int ix[4];
+            ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
-          T pa[4], pb[4];
+            for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
+            T pa[4], pb[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSP + ix[i]]; }
-          apply_wdag<T, TANG>(Gk, Vk, pa, pb);
+            for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSP + ix[i]]; }
+            apply_wdag<T, TANG>(Gk, Vk, pa, pb);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
+            for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
+          }
         }
         __syncthreads();
       }
@@ -643,6 +804,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       if (TANG) IO::store(abB, sY + TSP, base, xv, TS, tid);
     }
     __syncthreads();
+    s = sn;
+    x = xn;
   }
 
   // ---- per-workgroup environment partials: sum the 4 waves' 16x16 blocks, then combine
@@ -665,19 +828,19 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       __syncthreads();
       if (tid < kEnvVals) {
         const int which = tid >> 5, e = (tid >> 1) & 15, part = tid & 1;
-        const int x = e >> 2, y = e & 3;
+        const int ex = e >> 2, ey = e & 3;
         // row of A component (st: 0 a, 1 b; ri: 0 re, 1 im; amplitude k), column of B (0 psi, 1 dpsi)
 #define RI(st, ri, k) (8 * (st) + 4 * (ri) + (k))
 #define P(r, c) sM[(r) * 16 + (c)]
         double v;
         if (which == 0) {
-          v = part == 0 ? P(RI(0, 0, x), RI(0, 0, y)) + P(RI(0, 1, x), RI(0, 1, y))
-                        : P(RI(0, 0, x), RI(0, 1, y)) - P(RI(0, 1, x), RI(0, 0, y));
+          v = part == 0 ? P(RI(0, 0, ex), RI(0, 0, ey)) + P(RI(0, 1, ex), RI(0, 1, ey))
+                        : P(RI(0, 0, ex), RI(0, 1, ey)) - P(RI(0, 1, ex), RI(0, 0, ey));
         } else {
-          v = part == 0 ? P(RI(1, 0, x), RI(0, 0, y)) + P(RI(1, 1, x), RI(0, 1, y)) +
-                              P(RI(0, 0, x), RI(1, 0, y)) + P(RI(0, 1, x), RI(1, 1, y))
-                        : P(RI(1, 0, x), RI(0, 1, y)) - P(RI(1, 1, x), RI(0, 0, y)) +
-                              P(RI(0, 0, x), RI(1, 1, y)) - P(RI(0, 1, x), RI(1, 0, y));
+          v = part == 0 ? P(RI(1, 0, ex), RI(0, 0, ey)) + P(RI(1, 1, ex), RI(0, 1, ey)) +
+                              P(RI(0, 0, ex), RI(1, 0, ey)) + P(RI(0, 1, ex), RI(1, 1, ey))
+                        : P(RI(1, 0, ex), RI(0, 1, ey)) - P(RI(1, 1, ex), RI(0, 0, ey)) +
+                              P(RI(0, 0, ex), RI(1, 1, ey)) - P(RI(0, 1, ex), RI(1, 0, ey));
         }
 #undef P
 #undef RI
@@ -733,9 +896,58 @@ __global__ void __launch_bounds__(1024) k_reduce_env(const double* __restrict__ 
 // --------------------------------------------------------------------------------------------
 int grid_size(long long items) { return (int)(items < 2048 ? items : 2048); }
 
+namespace {
+// Workgroups of `kern` that fit on the current device at once (all CUs), cached per device.  The
+// persistent kernels split their tiles evenly over the grid, so a grid of exactly this many
+// workgroups runs in one round instead of leaving a partial second round.
+int resident_wgs(const void* kern, int slot) {
+  static int cache[16][16] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 2048;
+  int& c = cache[dev][slot];
+  if (c == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 || cus < 1)
+      return 2048;
+    c = per_cu * cus;
+  }
+  return c;
+}
+
+int pick_grid(long long items, int resident) {
+  const long long g = items < resident ? items : resident;
+  return (int)(g < 2048 ? g : 2048);
+}
+
+const void* fwd_kernel(Prec prec, int tangent, int* slot) {
+  *slot = (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0);
+  if (prec == P_C64) return tangent ? (const void*)k_fwd<float, true> : (const void*)k_fwd<float, false>;
+  return tangent ? (const void*)k_fwd<double, true> : (const void*)k_fwd<double, false>;
+}
+
+const void* bwd_kernel(Prec prec, int tangent, int* slot) {
+  *slot = 4 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0);
+  if (prec == P_C64) return tangent ? (const void*)k_bwd<float, true> : (const void*)k_bwd<float, false>;
+  return tangent ? (const void*)k_bwd<double, true> : (const void*)k_bwd<double, false>;
+}
+}  // namespace
+
+int fwd_grid(Prec prec, int tangent, long long items) {
+  int slot;
+  const void* k = fwd_kernel(prec, tangent, &slot);
+  return pick_grid(items, resident_wgs(k, slot));
+}
+
+int bwd_grid(Prec prec, int tangent, long long items) {
+  int slot;
+  const void* k = bwd_kernel(prec, tangent, &slot);
+  return pick_grid(items, resident_wgs(k, slot));
+}
+
 int launch_fwd(Prec prec, const FwdArgs& a, void* stream) {
   const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
-  dim3 grid(grid_size(items)), block(kThreads);
+  dim3 grid(fwd_grid(prec, a.tangent, items)), block(kThreads);
   hipStream_t st = (hipStream_t)stream;
   if (prec == P_C64) {
     if (a.tangent) hipLaunchKernelGGL((k_fwd<float, true>), grid, block, 0, st, a);
@@ -749,7 +961,7 @@ int launch_fwd(Prec prec, const FwdArgs& a, void* stream) {
 
 int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
   const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
-  dim3 grid(grid_size(items)), block(kThreads);
+  dim3 grid(bwd_grid(prec, a.tangent, items)), block(kThreads);
   hipStream_t st = (hipStream_t)stream;
   if (prec == P_C64) {
     if (a.tangent) hipLaunchKernelGGL((k_bwd<float, true>), grid, block, 0, st, a);
