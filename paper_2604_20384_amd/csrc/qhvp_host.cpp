@@ -51,7 +51,7 @@ int num_gates(int n, int L) {
 // lo = n-2-q and lo+1.  Greedy in increasing lo: the tile keeps the low
 // kCoalesceBits bits and adds each gate's two bits while it has room; the leftover
 // room is filled with the lowest unused bits (longer contiguous runs).
-void plan_layer(int n, int layer, int first_gate, std::vector<qhvp::PassDesc>& out) {
+void plan_layer_cap(int n, int layer, int first_gate, int cap, std::vector<qhvp::PassDesc>& out) {
   const int mbmax = std::min(n, qhvp::kMaxTileBits);
   std::vector<int> qs;
   for (int q = layer % 2; q + 1 < n; q += 2) qs.push_back(q);
@@ -66,7 +66,7 @@ void plan_layer(int n, int layer, int first_gate, std::vector<qhvp::PassDesc>& o
     for (int b = 0; b < cb; ++b) act[b] = true;
     int cnt = cb;
     std::vector<int> gates;
-    while (i < gl.size() && (int)gates.size() < qhvp::kMaxGates) {
+    while (i < gl.size() && (int)gates.size() < cap) {
       int lo = gl[i].first;
       int add = (act[lo] ? 0 : 1) + (act[lo + 1] ? 0 : 1);
       if (cnt + add > mbmax) break;
@@ -100,6 +100,17 @@ void plan_layer(int n, int layer, int first_gate, std::vector<qhvp::PassDesc>& o
   }
 }
 
+// Passes of at most kWaveLocalGates gates leave two tile bits untouched at mb = kMaxTileBits, which
+// the kernels use to give each wave its own quarter of the tile (no workgroup barrier between the
+// gates).  Take that cap whenever it needs no more passes than the full kMaxGates.
+void plan_layer(int n, int layer, int first_gate, std::vector<qhvp::PassDesc>& out) {
+  std::vector<qhvp::PassDesc> small, full;
+  plan_layer_cap(n, layer, first_gate, qhvp::kWaveLocalGates, small);
+  plan_layer_cap(n, layer, first_gate, qhvp::kMaxGates, full);
+  const auto& best = small.size() <= full.size() ? small : full;
+  out.insert(out.end(), best.begin(), best.end());
+}
+
 std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* layer_first_pass) {
   std::vector<qhvp::PassDesc> passes;
   int k = 0;
@@ -121,17 +132,40 @@ int lds_at(int t, int elem_bytes) {
 
 // Per-pass constants of the kernels' tile addressing: the tile-enumeration mask and, per gate, the
 // padded LDS offsets of the group-index bits (zero bits inserted at tlo < thi) and of tlo / thi.
+//
+// Group index bits 6, 7 select the wave.  Wave-local layout (full tile, two tile bits f0 < f1 that
+// no gate of the pass touches): bits 6, 7 sit on f0, f1 for every gate and bits 0..5 on the other
+// free bits in ascending order, so each wave only ever touches its own quarter of the tile.
+// Otherwise group bit i sits on the i-th tile bit other than tlo, thi (bits beyond the tile for
+// tiles of fewer than 2^kMaxTileBits amplitudes).
 void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
   for (auto& pd : passes) {
     pd.imask = 0;
     for (int i = 0; i < pd.n - pd.mb; ++i) pd.imask |= 1ULL << pd.ibit[i];
+    bool used[qhvp::kMaxTileBits] = {};
+    for (int j = 0; j < pd.ng; ++j) used[pd.tlo[j]] = used[pd.thi[j]] = true;
+    int f1 = -1, f0 = -1;
+    if (pd.mb == qhvp::kMaxTileBits) {
+      for (int b = qhvp::kMaxTileBits - 1; b >= 0 && f0 < 0; --b)
+        if (!used[b]) { if (f1 < 0) f1 = b; else f0 = b; }
+    }
+    pd.wave_local = f0 >= 0 ? 1 : 0;
     for (int j = 0; j < pd.ng; ++j) {
       const int lo = pd.tlo[j], hi = pd.thi[j];
-      for (int i = 0; i < 8; ++i) {
-        int pos = i + (i >= lo ? 1 : 0);
-        pos += (pos >= hi ? 1 : 0);
-        pd.goff[j][i] = lds_at(1 << pos, elem_bytes);
+      int pos[8];
+      if (pd.wave_local) {
+        int k = 0;
+        for (int b = 0; b < qhvp::kMaxTileBits; ++b)
+          if (b != lo && b != hi && b != f0 && b != f1) pos[k++] = b;
+        pos[6] = f0;
+        pos[7] = f1;
+      } else {
+        for (int i = 0; i < 8; ++i) {
+          pos[i] = i + (i >= lo ? 1 : 0);
+          pos[i] += (pos[i] >= hi ? 1 : 0);
+        }
       }
+      for (int i = 0; i < 8; ++i) pd.goff[j][i] = lds_at(1 << pos[i], elem_bytes);
       pd.aoff[j][0] = lds_at(1 << lo, elem_bytes);
       pd.aoff[j][1] = lds_at(1 << hi, elem_bytes);
     }
@@ -529,7 +563,7 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), b, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, bytes, pass_flops(p, b.pd, tangent, true)));
-      const int nwg = qhvp::bwd_grid(p->dprec(), tangent, (long long)p->Ns << (p->n - b.pd.mb));
+      const int nwg = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, (long long)p->Ns << (p->n - b.pd.mb));
       HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_reduce_env(envpart, nwg, b.pd, env, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_REDUCE, (double)nwg * b.pd.ng * qhvp::kEnvVals * 8, 0));

@@ -13,6 +13,7 @@ namespace qhvp {
 // bits are always active so that global loads and stores touch contiguous
 // runs.  The remaining (inactive) bits ibit[0..n-mb) enumerate the tiles.
 constexpr int kMaxGates = 5;
+constexpr int kWaveLocalGates = 4;   // passes of at most this many gates can run wave-local
 constexpr int kMaxTileBits = 10;
 constexpr int kMaxQubits = 30;
 constexpr int kThreads = 256;     // 4 wave64s; one 4-amplitude group per thread per gate at mb = 10
@@ -33,6 +34,7 @@ struct PassDesc {
   // the sum of goff[j][i] over its set bits i; tile bits tlo / thi add aoff[j][0] / aoff[j][1].
   int goff[kMaxGates][8];
   int aoff[kMaxGates][2];
+  int wave_local;               // 1: each wave owns the groups with its index in bits 6, 7 for all gates
 };
 
 enum Prec { P_C128 = 0, P_C64 = 1 };
@@ -77,7 +79,7 @@ struct BwdArgs {
 // the workgroups that are resident at once).
 int grid_size(long long items);
 int fwd_grid(Prec prec, int tangent, long long items);
-int bwd_grid(Prec prec, int tangent, long long items);
+int bwd_grid(Prec prec, int tangent, int ng, long long items);
 
 
 // Launchers (return a hipError_t as int).

@@ -155,10 +155,6 @@ __device__ __forceinline__ void apply_wdag(cptr<decltype(T::x)> G, cptr<decltype
   for (int i = 0; i < 4; ++i) { a[i] = na[i]; if (TANG) b[i] = nb[i]; }
 }
 
-__device__ __forceinline__ int opaque_int(int v) {
-  asm volatile("" : "+s"(v));
-  return v;
-}
 
 // Padded LDS index of tile element t: 16 spare bytes after every 256-byte row, so that the
 // power-of-two strides of gates on low tile bits spread over the banks while 16-byte vector
@@ -204,6 +200,17 @@ template <typename T> struct TileIO {
       if (elem(tid, v) < TS) *(V*)(g + base + xv[v]) = r;
     }
   }
+  // Stores split in two halves (LDS -> registers, registers -> memory), so that a tile's global
+  // stores can be issued after the next tile's loads have been waited for.
+  static __device__ __forceinline__ void read(V (&r)[NV], const T* lds, int tid) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r[v] = *(const V*)(lds + Lds<T>::at(elem(tid, v)));
+  }
+  static __device__ __forceinline__ void write(T* g, const V (&r)[NV], long long base, const int* xv, int TS, int tid) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      if (elem(tid, v) < TS) *(V*)(g + base + xv[v]) = r[v];
+  }
   static __device__ __forceinline__ T part(const V& r, int e) {
     T o;
     if constexpr (sizeof(T) == 8) { o.x = e ? r[2] : r[0]; o.y = e ? r[3] : r[1]; }
@@ -220,8 +227,6 @@ __device__ __forceinline__ void pin16(R (&v)[16]) {
                "v"(v[8]), "v"(v[9]), "v"(v[10]), "v"(v[11]), "v"(v[12]), "v"(v[13]), "v"(v[14]), "v"(v[15]));
 }
 
-// insert a zero bit at position b
-__device__ __forceinline__ int ins0(int v, int b) { return ((v >> b) << (b + 1)) | (v & ((1 << b) - 1)); }
 
 // --------------------------------------------------------------------------------------------
 // complex64 gate application on the matrix cores
@@ -251,19 +256,27 @@ __device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int
   return A;
 }
 
-// (p, d) <- W (p, d) on the 64 groups of one wave: four chains of 16 groups; all LDS reads first,
-// then the MFMAs, then the writes.  tl: this lane's LDS offset (amplitude g of group col, chain 0);
-// ch[c]: the wave-uniform offset of chain c.  Groups grp0 + 16c >= ngroups exist only in tiles of
-// fewer than 2^kMaxTileBits amplitudes; they read in-bounds LDS and are not written back.
+// (p, d) <- W (p, d) on the 64 groups of one wave: four chains of 16 groups; all LDS reads first
+// (pinned, so that they are in flight together rather than read-and-wait one at a time), then the
+// MFMAs, then the writes.  tl: this lane's LDS offset (amplitude g of group col, chain 0); ch[c]:
+// the wave-uniform offset of chain c.  Groups beyond the tile (tiles of fewer than 2^kMaxTileBits
+// amplitudes) hold tile indices >= 2^mb only: they are transformed and written back like the others,
+// which leaves a zeroed tail zero (W 0 = 0) and never touches an index below 2^mb.
 template <bool TANG>
-__device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* sD, int tl, const int (&ch)[4],
-                                             int grp0, int ngroups) {
+__device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* sD, int tl, const int (&ch)[4]) {
   float2 p[4], d[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     p[c] = sP[tl + ch[c]];
     if (TANG) d[c] = sD[tl + ch[c]];
   }
+  if (TANG)
+    asm volatile("" ::"v"(p[0].x), "v"(p[0].y), "v"(p[1].x), "v"(p[1].y), "v"(p[2].x), "v"(p[2].y), "v"(p[3].x),
+                 "v"(p[3].y), "v"(d[0].x), "v"(d[0].y), "v"(d[1].x), "v"(d[1].y), "v"(d[2].x), "v"(d[2].y),
+                 "v"(d[3].x), "v"(d[3].y));
+  else
+    asm volatile("" ::"v"(p[0].x), "v"(p[0].y), "v"(p[1].x), "v"(p[1].y), "v"(p[2].x), "v"(p[2].y), "v"(p[3].x),
+                 "v"(p[3].y));
   Mfma<float>::acc_t r[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
@@ -277,14 +290,21 @@ __device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* s
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    if (grp0 + 16 * c < ngroups) {
-      sP[tl + ch[c]] = make_float2(r[c][0], r[c][1]);
-      if (TANG) sD[tl + ch[c]] = make_float2(r[c][2], r[c][3]);
-    }
+    sP[tl + ch[c]] = make_float2(r[c][0], r[c][1]);
+    if (TANG) sD[tl + ch[c]] = make_float2(r[c][2], r[c][3]);
   }
 }
 
 __device__ __forceinline__ int bitsel(int v, int b, int off) { return ((v >> b) & 1) ? off : 0; }
+
+// Gate boundary inside a wave-local pass (every wave reads and writes only its own quarter of the
+// tile): the LDS accesses of one wave are performed in issue order, so only the compiler has to be
+// kept from moving LDS accesses across the boundary.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // Per-gate LDS offsets of a pass, staged in LDS once per workgroup (kOffs ints per gate slot:
 // goff[0..8), aoff[0..2)).  Read back after a barrier, they cannot be hoisted out of the tile loop
@@ -299,6 +319,13 @@ __device__ __forceinline__ void stage_offsets(const PassDesc& pd, int* sOff, int
 struct GateOff {
   int go[8], ao[2];
 };
+// Padded LDS indices of the 4 amplitudes of group g (2*b_hi + b_lo order).
+__device__ __forceinline__ void group_index(const GateOff& o, int g, int (&ix)[4]) {
+  int t = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) t += bitsel(g, i, o.go[i]);
+  ix[0] = t; ix[1] = t + o.ao[0]; ix[2] = t + o.ao[1]; ix[3] = t + o.ao[0] + o.ao[1];
+}
 __device__ __forceinline__ GateOff gate_offsets(const int* sOff, int j) {
   GateOff o;
 #pragma unroll
@@ -391,6 +418,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   const bool gen = (srcP == nullptr);
   const bool ovl = (a.ov_part != nullptr);
   const unsigned imask = (unsigned)pd.imask;
+  const bool wl = pd.wave_local != 0;
   const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);   // entry of X, Y behind this lane's operands
 
   if constexpr (kF32) stage_gates<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
@@ -421,6 +449,10 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
     }                                                                                               \
   }
   if (!gen && it0 < it1) QHVP_FWD_PREFETCH(s, x);
+  // The stores of tile t are issued after tile t+1's loads have been waited for: vmcnt counts
+  // stores too, so stores issued right before that wait would be waited for as well.
+  typename IO::V st0[IO::NV], st1[IO::NV];
+  long long st_base = -1;
 
   for (long long it = it0; it < it1; ++it) {
     const long long sbase = (long long)s * dim;
@@ -448,25 +480,26 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         if (TANG) *(typename IO::V*)(sD + sl) = pf1[v];
       }
     }
+    if (st_base >= 0) {
+      IO::write(dstP, st0, st_base, xv, TS, tid);
+      if (TANG) IO::write(dstD, st1, st_base, xv, TS, tid);
+    }
     __syncthreads();
     if (!gen && it + 1 < it1) QHVP_FWD_PREFETCH(sn, xn);
 
     for (int j = 0; j < ng; ++j) {
+      const GateOff O = gate_offsets(sOff, j);
       if constexpr (kF32) {
         int tl, ch[4];
-        w_offsets(gate_offsets(sOff, j), wave, lane, tl, ch);
+        w_offsets(O, wave, lane, tl, ch);
         const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_fwd, false, lane);
-        apply_w_mfma<TANG>(A, sP, sD, tl, ch, 64 * wave + (lane & 15), ngroups);
+        apply_w_mfma<TANG>(A, sP, sD, tl, ch);
       } else {
-        const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
         const auto Gk = opaque(G + 16 * pd.gidx[j]);
         const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
         if (tid < ngroups) {
-          const int t0 = ins0(ins0(tid, lo), hi);
           int ix[4];
-          ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
+          group_index(O, tid, ix);
           T p[4], d[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) { p[i] = sP[ix[i]]; if (TANG) d[i] = sD[ix[i]]; }
@@ -475,7 +508,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
           for (int i = 0; i < 4; ++i) { sP[ix[i]] = p[i]; if (TANG) sD[ix[i]] = d[i]; }
         }
       }
-      __syncthreads();
+      if (wl && j + 1 < ng) wave_sync();
+      else __syncthreads();
     }
 
     if (ovl) {
@@ -517,19 +551,25 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         a.ov_part[it * 4 + tid] = v;
       }
     } else {
-      IO::store(dstP, sP, base, xv, TS, tid);
-      if (TANG) IO::store(dstD, sD, base, xv, TS, tid);
+      IO::read(st0, sP, tid);
+      if (TANG) IO::read(st1, sD, tid);
+      st_base = base;
     }
     __syncthreads();
     s = sn;
     x = xn;
+  }
+  if (st_base >= 0) {
+    IO::write(dstP, st0, st_base, xv, TS, tid);
+    if (TANG) IO::write(dstD, st1, st_base, xv, TS, tid);
   }
 }
 
 // --------------------------------------------------------------------------------------------
 // Backward pass with environment accumulation
 // --------------------------------------------------------------------------------------------
-template <typename R, bool TANG>
+// MAXG: most gates a pass may hold (the per-gate MFMA operands and accumulators are registers).
+template <typename R, bool TANG, int MAXG>
 __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   using T = typename CT<R>::T;
   using M = Mfma<R>;
@@ -546,7 +586,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sM[16 * 16];
   // complex64: FP64 running sums of the per-tile FP32 MFMA accumulators, one column per thread
-  __shared__ double sAcc[kF32 ? kMaxGates * 4 * kThreads : 1];
+  __shared__ double sAcc[kF32 ? MAXG * 4 * kThreads : 1];
   __shared__ float2 sGV[kF32 ? kMaxGates * 32 : 1];
   __shared__ int sOff[kMaxGates * kOffs];
 
@@ -569,6 +609,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   const T* __restrict__ samp = (const T*)a.samples;
   const bool gen = (srcP == nullptr);
   const unsigned imask = (unsigned)pd.imask;
+  const bool wl = pd.wave_local != 0;
   const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);
   const int e_bwd = 4 * (lane >> 4) + ((lane >> 2) & 3);
 
@@ -588,17 +629,17 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   // the a / psi arrays (in bounds) and their products are discarded.
   const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSP + cri;  // in units of R
 
-  acc_t acc[kMaxGates];
+  acc_t acc[MAXG];
 #pragma unroll
-  for (int j = 0; j < kMaxGates; ++j) {
+  for (int j = 0; j < MAXG; ++j) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[j][r] = 0;
   }
   if constexpr (kF32) {
-    for (int i = tid; i < kMaxGates * 4 * kThreads; i += kThreads) sAcc[i] = 0;
+    for (int i = tid; i < MAXG * 4 * kThreads; i += kThreads) sAcc[i] = 0;
   }
-  // Groups g >= ngroups (only when mb < kMaxTileBits) map to tile indices >= 2^mb, which no tile
-  // operation writes: zero them once so that their MFMA operands are zero.
+  // Groups g >= ngroups (only when mb < kMaxTileBits) map to tile indices >= 2^mb: zero them once so
+  // that their MFMA operands are zero (the gate applications keep them zero).
   for (int t = TS + tid; t < TSMAX; t += kThreads) {
     sX[LD::at(t)] = cz<T>(); sY[LD::at(t)] = cz<T>();
     if (TANG) { sX[TSP + LD::at(t)] = cz<T>(); sY[TSP + LD::at(t)] = cz<T>(); }
@@ -629,6 +670,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     }                                                                                               \
   }
   if (common && it0 < it1) QHVP_BWD_PREFETCH(s, x);
+  // deferred stores of the previous tile's (a, b), as in k_fwd (not with 5-gate passes, where the
+  // registers they hold would halve the occupancy)
+  constexpr bool kDefer = MAXG <= kWaveLocalGates;
+  typename IO::V st0[IO::NV], st1[IO::NV];
+  long long st_base = -1;
 
   for (long long it = it0; it < it1; ++it) {
     const long long sbase = (long long)s * dim;
@@ -687,13 +733,17 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       if (TANG) IO::load(sX + TSP, srcD, base, xv, TS, tid);
     }
     }
+    if (st_base >= 0) {
+      IO::write(abA, st0, st_base, xv, TS, tid);
+      if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+    }
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
 
     // ---- forward recompute inside the tile; keep this lane's MFMA B operands of every gate
-    R bop[kMaxGates][16];
+    R bop[MAXG][16];
 #pragma unroll
-    for (int j = 0; j < kMaxGates; ++j) {
+    for (int j = 0; j < MAXG; ++j) {
       if (j < ng) {
         const GateOff O = gate_offsets(sOff, j);
         const int* go = O.go;
@@ -714,17 +764,13 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
             int tw, ch[4];
             w_offsets(O, uwave, lane, tw, ch);
             const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_fwd, false, lane);
-            apply_w_mfma<TANG>(A, sX, sX + TSP, tw, ch, 64 * uwave + (lane & 15), ngroups);
+            apply_w_mfma<TANG>(A, sX, sX + TSP, tw, ch);
           } else {
-            const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
             const auto Gk = opaque(G + 16 * pd.gidx[j]);
             const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
             if (tid < ngroups) {
-              const int t0 = ins0(ins0(tid, lo), hi);
               int ix[4];
-              ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
+              group_index(O, tid, ix);
               T p[4], d[4];
 #pragma unroll
               for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
@@ -733,14 +779,15 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
               for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSP + ix[i]] = d[i]; }
             }
           }
-          __syncthreads();
+          if (wl) wave_sync();
+          else __syncthreads();
         }
       }
     }
 
     // ---- backward through the pass: accumulate environments, then undo the gate
 #pragma unroll
-    for (int j = kMaxGates - 1; j >= 0; --j) {
+    for (int j = MAXG - 1; j >= 0; --j) {
       if (j < ng) {
         const GateOff O = gate_offsets(sOff, j);
         const int* go = O.go;
@@ -762,17 +809,13 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           int tw, ch[4];
           w_offsets(O, uwave, lane, tw, ch);
           const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_bwd, true, lane);
-          apply_w_mfma<TANG>(A, sY, sY + TSP, tw, ch, 64 * uwave + (lane & 15), ngroups);
+          apply_w_mfma<TANG>(A, sY, sY + TSP, tw, ch);
         } else {
-          const int lo = opaque_int(pd.tlo[j]), hi = opaque_int(pd.thi[j]);
           const auto Gk = opaque(G + 16 * pd.gidx[j]);
           const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
           if (tid < ngroups) {
-            const int t0 = ins0(ins0(tid, lo), hi);
             int ix[4];
-            ix[0] = t0; ix[1] = t0 | (1 << lo); ix[2] = t0 | (1 << hi); ix[3] = ix[1] | (1 << hi);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) ix[i] = LD::at(ix[i]);
+            group_index(O, tid, ix);
             T pa[4], pb[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSP + ix[i]]; }
@@ -781,14 +824,15 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
             for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
           }
         }
-        __syncthreads();
+        if (wl && j > 0) wave_sync();
+        else __syncthreads();
       }
     }
 
     // ---- complex64: one tile's FP32 partial sums into the FP64 accumulators (LDS, own column)
     if constexpr (kF32) {
 #pragma unroll
-      for (int j = 0; j < kMaxGates; ++j) {
+      for (int j = 0; j < MAXG; ++j) {
         if (j < ng) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
@@ -800,18 +844,28 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     }
 
     if (a.store_ab) {
-      IO::store(abA, sY, base, xv, TS, tid);
-      if (TANG) IO::store(abB, sY + TSP, base, xv, TS, tid);
+      if constexpr (kDefer) {
+        IO::read(st0, sY, tid);
+        if (TANG) IO::read(st1, sY + TSP, tid);
+        st_base = base;
+      } else {
+        IO::store(abA, sY, base, xv, TS, tid);
+        if (TANG) IO::store(abB, sY + TSP, base, xv, TS, tid);
+      }
     }
     __syncthreads();
     s = sn;
     x = xn;
   }
+  if (st_base >= 0) {
+    IO::write(abA, st0, st_base, xv, TS, tid);
+    if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+  }
 
   // ---- per-workgroup environment partials: sum the 4 waves' 16x16 blocks, then combine
   double* sRed = (double*)sY;   // kThreads * 4 doubles fit in sY for both precisions
 #pragma unroll
-  for (int j = 0; j < kMaxGates; ++j) {
+  for (int j = 0; j < MAXG; ++j) {
     if (j < ng) {
 #pragma unroll
       for (int r = 0; r < 4; ++r)
@@ -926,10 +980,16 @@ const void* fwd_kernel(Prec prec, int tangent, int* slot) {
   return tangent ? (const void*)k_fwd<double, true> : (const void*)k_fwd<double, false>;
 }
 
-const void* bwd_kernel(Prec prec, int tangent, int* slot) {
-  *slot = 4 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0);
-  if (prec == P_C64) return tangent ? (const void*)k_bwd<float, true> : (const void*)k_bwd<float, false>;
-  return tangent ? (const void*)k_bwd<double, true> : (const void*)k_bwd<double, false>;
+template <int MAXG>
+const void* bwd_kernel_g(Prec prec, int tangent) {
+  if (prec == P_C64) return tangent ? (const void*)k_bwd<float, true, MAXG> : (const void*)k_bwd<float, false, MAXG>;
+  return tangent ? (const void*)k_bwd<double, true, MAXG> : (const void*)k_bwd<double, false, MAXG>;
+}
+
+const void* bwd_kernel(Prec prec, int tangent, int ng, int* slot) {
+  const bool small = ng <= kWaveLocalGates;
+  *slot = 4 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0) + (small ? 4 : 0);
+  return small ? bwd_kernel_g<kWaveLocalGates>(prec, tangent) : bwd_kernel_g<kMaxGates>(prec, tangent);
 }
 }  // namespace
 
@@ -939,9 +999,9 @@ int fwd_grid(Prec prec, int tangent, long long items) {
   return pick_grid(items, resident_wgs(k, slot));
 }
 
-int bwd_grid(Prec prec, int tangent, long long items) {
+int bwd_grid(Prec prec, int tangent, int ng, long long items) {
   int slot;
-  const void* k = bwd_kernel(prec, tangent, &slot);
+  const void* k = bwd_kernel(prec, tangent, ng, &slot);
   return pick_grid(items, resident_wgs(k, slot));
 }
 
@@ -961,16 +1021,11 @@ int launch_fwd(Prec prec, const FwdArgs& a, void* stream) {
 
 int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
   const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
-  dim3 grid(bwd_grid(prec, a.tangent, items)), block(kThreads);
-  hipStream_t st = (hipStream_t)stream;
-  if (prec == P_C64) {
-    if (a.tangent) hipLaunchKernelGGL((k_bwd<float, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_bwd<float, false>), grid, block, 0, st, a);
-  } else {
-    if (a.tangent) hipLaunchKernelGGL((k_bwd<double, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_bwd<double, false>), grid, block, 0, st, a);
-  }
-  return (int)hipGetLastError();
+  int slot;
+  const void* k = bwd_kernel(prec, a.tangent, a.pd.ng, &slot);
+  dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
+  void* args[] = {(void*)&a};
+  return (int)hipLaunchKernel(k, grid, block, args, 0, (hipStream_t)stream);
 }
 
 int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream) {
