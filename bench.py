@@ -196,8 +196,9 @@ def main():
     else:
         roof = {"bound": unit_name, "achieved": round(tfs, 2), "peak": comp_peak, "unit": "TFLOP/s",
                 "frac": round(frac_comp, 4)}
-    kname = (f"k_bwd<{'float' if args.precision == 'c64' else 'double'},true>" if dom == "backward"
-             else f"k_fwd<{'float' if args.precision == 'c64' else 'double'},true>")
+    rt = "float" if args.precision == "c64" else "double"
+    bwd_name = "k_bwd_out" if gp.backward_from_outputs else "k_bwd"
+    kname = f"{bwd_name}<{rt},true>" if dom == "backward" else f"k_fwd<{rt},true>"
     traffic = measured_traffic(kname) if (n, L, ns) == (20, 20, 256) else None
     roof.update({"traffic": traffic, "kernel": kname,
                  "avg_launch_ms": round(avg_ms, 4), "launches": st["launches"],

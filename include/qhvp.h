@@ -116,6 +116,14 @@ void qhvp_problem_destroy(qhvp_problem* p);
 /* Cost C and fidelity F for gates G (K*16 complex, host).  One forward sweep (Sec. III, single-pass overlap). */
 qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fidelity);
 
+/* Backward sweep algorithm (gradient and HVP calls).  When every gate satisfies
+ * |G_k|_F |G_k^-1|_F <= 8 (unitary gates: 4), each backward pass starts from the forward states at
+ * the pass OUTPUT and undoes the gates on them (psi <- G^-1 psi, dpsi <- G^-1 dpsi - G^-1 V G^-1 psi)
+ * while it undoes them on the backward states; the environments taken against output states are
+ * mapped back on the host in FP64 (E = Et G^-T, D = (Dt - E V^T) G^-T).  Otherwise, or when the
+ * environment variable QHVP_BACKWARD is "recompute", each pass recomputes the forward states
+ * inside the tile from the pass input.  Both give the same sums up to rounding. */
+
 /* Cost and gradient (K*16 complex, host) of C at G: forward sweep, then the backward
  * sweep accumulating the environments (Eq. environment, Alg. 2 "postprocess gradient"). */
 qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom,
@@ -154,6 +162,10 @@ qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega);
 /* Problem facts: n_passes is the number of gate passes per sweep of the ansatz. */
 qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size_t* ws_bytes,
                               int* segments);
+
+/* 1 if the last gradient / HVP forward phase chose the backward sweep from pass outputs (see
+ * above), 0 if it chose recomputation; -1 for a NULL problem. */
+int qhvp_backward_from_outputs(const qhvp_problem* p);
 
 /* Milliseconds spent on the device by the last cost / forward(+backward) evaluation (HIP events). */
 double qhvp_last_device_ms(const qhvp_problem* p);

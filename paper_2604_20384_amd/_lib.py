@@ -56,6 +56,7 @@ _SIGS = {
     "qhvp_overlaps": (C.c_int, [_vp, _dp, _dp]),
     "qhvp_problem_info": (C.c_int, [_vp, _ip, _ip, _szp, _ip]),
     "qhvp_last_device_ms": (C.c_double, [_vp]),
+    "qhvp_backward_from_outputs": (C.c_int, [_vp]),
     "qhvp_set_profiling": (C.c_int, [_vp, C.c_int]),
     "qhvp_kernel_stats": (C.c_int, [_vp, C.c_int, _dp, C.POINTER(C.c_longlong), _dp, _dp]),
     "qhvp_project": (C.c_int, [C.c_int, _dp, _dp, _dp]),

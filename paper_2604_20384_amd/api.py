@@ -220,6 +220,11 @@ class Problem:
     def last_device_ms(self) -> float:
         return lib.qhvp_last_device_ms(self.handle)
 
+    @property
+    def backward_from_outputs(self) -> bool:
+        """Whether the last gradient / HVP used the backward sweep from pass outputs (inverse gates)."""
+        return bool(lib.qhvp_backward_from_outputs(self.handle))
+
     def close(self):
         if getattr(self, "handle", None):
             lib.qhvp_problem_destroy(self.handle)

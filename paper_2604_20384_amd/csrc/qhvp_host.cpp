@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <complex>
 #include <cstdio>
 #include <cstring>
@@ -201,7 +202,7 @@ struct Layout {
   size_t off_phi0 = 0, off_slots = 0, off_small = 0, total = 0;
   size_t slot_bytes = 0;
   // small buffers (offsets from off_small)
-  size_t o_samples, o_gates, o_dirs, o_uref, o_tov, o_ovpart, o_envpart, o_env;
+  size_t o_samples, o_gates, o_dirs, o_igates, o_uref, o_tov, o_ovpart, o_envpart, o_env;
 };
 
 bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_every, int tangent,
@@ -228,6 +229,7 @@ bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_
   lay.o_samples = o; o = align_up(o + (size_t)Ns * n * 2 * amp);
   lay.o_gates = o;   o = align_up(o + (size_t)K * 16 * amp);
   lay.o_dirs = o;    o = align_up(o + (size_t)K * 16 * amp);
+  lay.o_igates = o;  o = align_up(o + (size_t)K * 32 * amp);
   lay.o_uref = o;    o = align_up(o + (size_t)Kr * 16 * amp);
   lay.o_tov = o;     o = align_up(o + (size_t)Ns * 4 * sizeof(double));
   // overlap partials: the ansatz and U_ref plans share the tile count of their passes
@@ -352,11 +354,15 @@ struct qhvp_problem {
   // host staging (pinned)
   void* h_gates;   // K*16 amplitudes (device precision)
   void* h_dirs;
+  void* h_igates;  // K*32 amplitudes: G^-1 | -G^-1 V G^-1 per gate (device precision)
   double* h_tov;   // Ns*4
   double* h_env;   // K*64
   std::vector<double> last_T, last_Om;
   // two-phase evaluation: a forward sweep leaves its checkpoints for one backward sweep
   int fwd_ready = 0, fwd_tangent = 0;
+  // backward from pass-output states (all gates well conditioned): FP64 G^-1 and V of that sweep
+  int bwd_inverse = 0;
+  std::vector<cd> bwd_Gi, bwd_V;
   qhvp_geometry fwd_geom = QHVP_EUCLIDEAN;
   std::vector<double> fwd_G, fwd_V;
   hipEvent_t ev0, ev1;
@@ -481,8 +487,9 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
     a.src_psi = src;
     a.src_dpsi = src ? p->second(src) : nullptr;
     if (mode != 0 && q == np - 1) {
-      a.dst_psi = nullptr;
-      a.dst_dpsi = nullptr;
+      // the backward sweep from pass outputs starts from the final states (kept in the working slot)
+      a.dst_psi = (mode == 1 && p->bwd_inverse) ? p->work() : nullptr;
+      a.dst_dpsi = a.dst_psi ? p->second(p->work()) : nullptr;
       a.phi0 = p->phi0();
       a.ov_part = ovpart;
     } else {
@@ -491,7 +498,7 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
     }
     {
       const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
-      const double bytes = (a.src_psi ? nst * S : 0) + (a.ov_part ? S : nst * S);
+      const double bytes = (a.src_psi ? nst * S : 0) + (a.ov_part ? S : 0) + (a.dst_psi ? nst * S : 0);
       HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_FORWARD, bytes, pass_flops(p, a.pd, tangent, false)));
@@ -547,7 +554,10 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       b.tangent = tangent;
       b.gates = gates;
       b.dirs = dirs;
+      b.igates = p->small(p->lay.o_igates);
+      // forward states: the pass input (recomputing kernel) or the pass output (inverse kernel)
       char* src = q == s0 ? start : p->segbuf(q - s0);
+      if (p->bwd_inverse) src = q + 1 < s1 ? p->segbuf(q + 1 - s0) : (j == J - 1 ? ab : p->ckpt(j + 1));
       b.src_psi = src;
       b.src_dpsi = src ? p->second(src) : nullptr;
       b.samples = samples;
@@ -561,9 +571,10 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
       const double bytes = (b.fold ? S : nst * S) + (src ? nst * S : 0) + (b.store_ab ? nst * S : 0);
       HIP_TRY(prof_begin(p));
-      LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), b, p->stream));
+      if (p->bwd_inverse) LAUNCH_TRY(qhvp::launch_bwd_out(p->dprec(), b, p->stream));
+      else LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), b, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, bytes, pass_flops(p, b.pd, tangent, true)));
-      const int nwg = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, (long long)p->Ns << (p->n - b.pd.mb));
+      const int nwg = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, (long long)p->Ns << (p->n - b.pd.mb), p->bwd_inverse);
       HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_reduce_env(envpart, nwg, b.pd, env, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_REDUCE, (double)nwg * b.pd.ng * qhvp::kEnvVals * 8, 0));
@@ -592,6 +603,72 @@ qhvp_status finish_call(qhvp_problem* p, int copy_env, int tangent) {
   return QHVP_OK;
 }
 
+// The backward sweep may start each pass from its OUTPUT forward states and undo the gates on them
+// (k_bwd_out) when every gate is well conditioned: then the inverse gates G^-1 and Y = -G^-1 V G^-1
+// (FP64 here, device precision on the device) are staged.  Condition: |G|_F |G^-1|_F <= 8 (4 for a
+// unitary gate), so that undoing the at most kMaxGates gates of a pass loses at most a few bits.
+void prepare_inverse(qhvp_problem* p, const double* G, const double* V) {
+  p->bwd_inverse = 0;
+  const char* choice = std::getenv("QHVP_BACKWARD");
+  if (choice && std::strcmp(choice, "recompute") == 0) return;
+  p->bwd_Gi.assign((size_t)p->K * 16, cd(0));
+  p->bwd_V.assign((size_t)p->K * 16, cd(0));
+  std::vector<double> stage((size_t)p->K * 64);
+  for (int k = 0; k < p->K; ++k) {
+    M4 g, gi, v, t, y;
+    load4(G + (size_t)k * 32, g);
+    if (!inv4(g, gi) || fro4(g) * fro4(gi) > 8.0) return;
+    if (V) load4(V + (size_t)k * 32, v);
+    else for (int i = 0; i < 16; ++i) v[i] = 0;
+    mul4(gi, v, t);
+    mul4(t, gi, y);
+    for (int i = 0; i < 16; ++i) {
+      p->bwd_Gi[(size_t)k * 16 + i] = gi[i];
+      p->bwd_V[(size_t)k * 16 + i] = v[i];
+      stage[(size_t)k * 64 + 2 * i] = gi[i].real();
+      stage[(size_t)k * 64 + 2 * i + 1] = gi[i].imag();
+      stage[(size_t)k * 64 + 32 + 2 * i] = -y[i].real();
+      stage[(size_t)k * 64 + 32 + 2 * i + 1] = -y[i].imag();
+    }
+  }
+  to_device_precision(p, stage.data(), (size_t)p->K * 32, p->h_igates);
+  p->bwd_inverse = 1;
+}
+
+// Output-side environment sums of the inverse backward sweep -> input-side ones, per gate (FP64):
+// E = Et G^-T, D = (Dt - E V^T) G^-T, in place in h_env (E at [0, 32), D at [32, 64), entry 4x+y).
+void map_output_envs(qhvp_problem* p, int tangent) {
+  for (int k = 0; k < p->K; ++k) {
+    double* e = p->h_env + (size_t)k * 64;
+    const cd* gi = &p->bwd_Gi[(size_t)k * 16];
+    const cd* v = &p->bwd_V[(size_t)k * 16];
+    cd Et[16], Dt[16], E[16], W[16];
+    for (int i = 0; i < 16; ++i) { Et[i] = cd(e[2 * i], e[2 * i + 1]); Dt[i] = cd(e[32 + 2 * i], e[32 + 2 * i + 1]); }
+    for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y) {
+        cd sE = 0;
+        for (int z = 0; z < 4; ++z) sE += Et[4 * x + z] * gi[4 * y + z];
+        E[4 * x + y] = sE;
+      }
+    for (int x = 0; x < 4; ++x)   // W = Dt - E V^T
+      for (int z = 0; z < 4; ++z) {
+        cd w = Dt[4 * x + z];
+        if (tangent)
+          for (int u = 0; u < 4; ++u) w -= E[4 * x + u] * v[4 * z + u];
+        W[4 * x + z] = w;
+      }
+    for (int x = 0; x < 4; ++x)
+      for (int y = 0; y < 4; ++y) {
+        cd sD = 0;
+        for (int z = 0; z < 4; ++z) sD += W[4 * x + z] * gi[4 * y + z];
+        e[2 * (4 * x + y)] = E[4 * x + y].real();
+        e[2 * (4 * x + y) + 1] = E[4 * x + y].imag();
+        e[32 + 2 * (4 * x + y)] = sD.real();
+        e[32 + 2 * (4 * x + y) + 1] = sD.imag();
+      }
+  }
+}
+
 // Forward phase.  mode 0: cost only (no checkpoints kept); 1: gradient sweep; 2: HVP sweep.  Uploads
 // G (and V), sweeps, and brings the per-sample overlaps T_s (and Omega_s) back to the host.
 qhvp_status phase_forward(qhvp_problem* p, const double* G, const double* V, int mode) {
@@ -606,6 +683,12 @@ qhvp_status phase_forward(qhvp_problem* p, const double* G, const double* V, int
     HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_dirs), p->h_dirs, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
   }
   const int tangent = mode == 2 ? 1 : 0;
+  if (mode != 0) {
+    prepare_inverse(p, G, tangent ? V : nullptr);
+    if (p->bwd_inverse)
+      HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_igates), p->h_igates, (size_t)p->K * 32 * p->amp(), hipMemcpyHostToDevice,
+                             p->stream));
+  }
   qhvp_status st = mode == 0 ? forward_sweep(p, p->passes, p->small(p->lay.o_gates), nullptr, 0, 2)
                              : forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent, 1);
   if (st) return st;
@@ -637,7 +720,10 @@ qhvp_status phase_backward(qhvp_problem* p) {
   HIP_TRY(hipEventRecord(p->ev0, p->stream));
   qhvp_status st = backward_sweep(p, p->fwd_tangent);
   if (st) return st;
-  return finish_call(p, 1, p->fwd_tangent);
+  st = finish_call(p, 1, p->fwd_tangent);
+  if (st) return st;
+  if (p->bwd_inverse) map_output_envs(p, p->fwd_tangent);
+  return QHVP_OK;
 }
 
 // Alg. 2 post-processing over samples: F = mean |T_s|^2; with the folded environments
@@ -725,7 +811,7 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
   p->seg = plan_segments(n, L, ckpt_every);
   p->lay = lay;
   p->last_ms = 0;
-  p->h_gates = p->h_dirs = nullptr;
+  p->h_gates = p->h_dirs = p->h_igates = nullptr;
   p->h_tov = p->h_env = nullptr;
   p->ev0 = p->ev1 = nullptr;
   auto cleanup_fail = [&](qhvp_status st, const std::string& msg) {
@@ -744,6 +830,7 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
   const size_t amp = p->amp();
   const size_t stage = std::max((size_t)std::max(p->K, Kr) * 16, (size_t)n_samples * n * 2) * amp;
   if (hipHostMalloc(&p->h_gates, stage) != hipSuccess || hipHostMalloc(&p->h_dirs, stage) != hipSuccess ||
+      hipHostMalloc(&p->h_igates, (size_t)p->K * 32 * amp) != hipSuccess ||
       hipHostMalloc((void**)&p->h_tov, (size_t)n_samples * 4 * sizeof(double)) != hipSuccess ||
       hipHostMalloc((void**)&p->h_env, (size_t)p->K * qhvp::kEnvVals * sizeof(double)) != hipSuccess)
     return cleanup_fail(QHVP_ERR_NOMEM, "pinned host allocation failed");
@@ -772,6 +859,7 @@ void qhvp_problem_destroy(qhvp_problem* p) {
   if (p->owns_ws && p->ws) hipFree(p->ws);
   if (p->h_gates) hipHostFree(p->h_gates);
   if (p->h_dirs) hipHostFree(p->h_dirs);
+  if (p->h_igates) hipHostFree(p->h_igates);
   if (p->h_tov) hipHostFree(p->h_tov);
   if (p->h_env) hipHostFree(p->h_env);
   if (p->ev0) hipEventDestroy(p->ev0);
@@ -945,6 +1033,8 @@ qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size
   if (segments) *segments = (int)p->seg.size();
   return QHVP_OK;
 }
+
+int qhvp_backward_from_outputs(const qhvp_problem* p) { return p ? p->bwd_inverse : -1; }
 
 double qhvp_last_device_ms(const qhvp_problem* p) { return p ? p->last_ms : 0.0; }
 

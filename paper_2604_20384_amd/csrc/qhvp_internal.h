@@ -72,6 +72,9 @@ struct BwdArgs {
   int fold;
   int store_ab;
   double* env_part;
+  // launch_bwd_out only: forward states are the pass OUTPUT (src_*), igates = G^-1 | -G^-1 V G^-1
+  // per gate (32 complex), fold passes read src_* too (no generated states)
+  const void* igates;
 };
 
 // Upper bound of the workgroup count of any pass kernel over `items` tiles (sizes per-workgroup
@@ -79,12 +82,14 @@ struct BwdArgs {
 // the workgroups that are resident at once).
 int grid_size(long long items);
 int fwd_grid(Prec prec, int tangent, long long items);
-int bwd_grid(Prec prec, int tangent, int ng, long long items);
+int bwd_grid(Prec prec, int tangent, int ng, long long items, int from_output);
 
 
 // Launchers (return a hipError_t as int).
 int launch_fwd(Prec prec, const FwdArgs& a, void* stream);
 int launch_bwd(Prec prec, const BwdArgs& a, void* stream);
+// Backward pass from the pass-output forward states (see k_bwd_out); same grid as launch_bwd.
+int launch_bwd_out(Prec prec, const BwdArgs& a, void* stream);
 // tov[s] = (T_s, Omega_s) = sum over tiles of ov_part.
 int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream);
 // env[gidx[j]][0..64) = sum over wg of env_part[wg][j][0..64), for j < ng.

@@ -243,8 +243,7 @@ __device__ __forceinline__ void pin16(R (&v)[16]) {
 //   step 2: (0, 0, Re x, Im x)[l%4]            step 3: (0, 0, -Im x, Re x)[l%4]
 // with x, y the entries [(l/4)%4][l/16] of X, Y (forward), or the conjugates of the entries
 // [l/16][(l/4)%4] (the form [[X^dag, 0], [Y^dag, X^dag]] of the backward recursion).
-__device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int e, bool conj_, int lane) {
-  float2 x = X[e], y = Y[e];
+__device__ __forceinline__ qv4f w_operands_xy(float2 x, float2 y, bool conj_, int lane) {
   if (conj_) { x.y = -x.y; y.y = -y.y; }
   const bool odd = (lane & 1) != 0, low = (lane & 2) == 0;
   const float2 u = low ? x : y;
@@ -255,6 +254,9 @@ __device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int
   A[3] = low ? 0.f : (odd ? x.x : -x.y);
   return A;
 }
+__device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int e, bool conj_, int lane) {
+  return w_operands_xy(X[e], Y[e], conj_, lane);
+}
 
 // (p, d) <- W (p, d) on the 64 groups of one wave: four chains of 16 groups; all LDS reads first
 // (pinned, so that they are in flight together rather than read-and-wait one at a time), then the
@@ -263,36 +265,53 @@ __device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int
 // amplitudes) hold tile indices >= 2^mb only: they are transformed and written back like the others,
 // which leaves a zeroed tail zero (W 0 = 0) and never touches an index below 2^mb.
 template <bool TANG>
-__device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* sD, int tl, const int (&ch)[4]) {
+struct WTile {
   float2 p[4], d[4];
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    p[c] = sP[tl + ch[c]];
-    if (TANG) d[c] = sD[tl + ch[c]];
-  }
-  if (TANG)
-    asm volatile("" ::"v"(p[0].x), "v"(p[0].y), "v"(p[1].x), "v"(p[1].y), "v"(p[2].x), "v"(p[2].y), "v"(p[3].x),
-                 "v"(p[3].y), "v"(d[0].x), "v"(d[0].y), "v"(d[1].x), "v"(d[1].y), "v"(d[2].x), "v"(d[2].y),
-                 "v"(d[3].x), "v"(d[3].y));
-  else
-    asm volatile("" ::"v"(p[0].x), "v"(p[0].y), "v"(p[1].x), "v"(p[1].y), "v"(p[2].x), "v"(p[2].y), "v"(p[3].x),
-                 "v"(p[3].y));
   Mfma<float>::acc_t r[4];
+  __device__ __forceinline__ void load(const float2* sP, const float2* sD, int tl, const int (&ch)[4]) {
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    r[c][0] = 0; r[c][1] = 0; r[c][2] = 0; r[c][3] = 0;
-    r[c] = Mfma<float>::step(A[0], p[c].x, r[c]);
-    r[c] = Mfma<float>::step(A[1], p[c].y, r[c]);
-    if (TANG) {
-      r[c] = Mfma<float>::step(A[2], d[c].x, r[c]);
-      r[c] = Mfma<float>::step(A[3], d[c].y, r[c]);
+    for (int c = 0; c < 4; ++c) {
+      p[c] = sP[tl + ch[c]];
+      if (TANG) d[c] = sD[tl + ch[c]];
     }
   }
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    sP[tl + ch[c]] = make_float2(r[c][0], r[c][1]);
-    if (TANG) sD[tl + ch[c]] = make_float2(r[c][2], r[c][3]);
+  __device__ __forceinline__ void pin() {
+    if (TANG)
+      asm volatile("" ::"v"(p[0].x), "v"(p[0].y), "v"(p[1].x), "v"(p[1].y), "v"(p[2].x), "v"(p[2].y), "v"(p[3].x),
+                   "v"(p[3].y), "v"(d[0].x), "v"(d[0].y), "v"(d[1].x), "v"(d[1].y), "v"(d[2].x), "v"(d[2].y),
+                   "v"(d[3].x), "v"(d[3].y));
+    else
+      asm volatile("" ::"v"(p[0].x), "v"(p[0].y), "v"(p[1].x), "v"(p[1].y), "v"(p[2].x), "v"(p[2].y), "v"(p[3].x),
+                   "v"(p[3].y));
   }
+  __device__ __forceinline__ void mfma(const qv4f A) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      r[c][0] = 0; r[c][1] = 0; r[c][2] = 0; r[c][3] = 0;
+      r[c] = Mfma<float>::step(A[0], p[c].x, r[c]);
+      r[c] = Mfma<float>::step(A[1], p[c].y, r[c]);
+      if (TANG) {
+        r[c] = Mfma<float>::step(A[2], d[c].x, r[c]);
+        r[c] = Mfma<float>::step(A[3], d[c].y, r[c]);
+      }
+    }
+  }
+  __device__ __forceinline__ void store(float2* sP, float2* sD, int tl, const int (&ch)[4]) const {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      sP[tl + ch[c]] = make_float2(r[c][0], r[c][1]);
+      if (TANG) sD[tl + ch[c]] = make_float2(r[c][2], r[c][3]);
+    }
+  }
+};
+
+template <bool TANG>
+__device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* sD, int tl, const int (&ch)[4]) {
+  WTile<TANG> w;
+  w.load(sP, sD, tl, ch);
+  w.pin();
+  w.mfma(A);
+  w.store(sP, sD, tl, ch);
 }
 
 __device__ __forceinline__ int bitsel(int v, int b, int off) { return ((v >> b) & 1) ? off : 0; }
@@ -319,12 +338,40 @@ __device__ __forceinline__ void stage_offsets(const PassDesc& pd, int* sOff, int
 struct GateOff {
   int go[8], ao[2];
 };
+// What one backward step of k_bwd_out reads from the per-pass LDS tables, loaded one step ahead
+// so that the step does not start with a chain of LDS round trips: the gate's offsets (made
+// scalar with readfirstlane when used) and, for complex64, this lane's entries of G, V (W^dag
+// operands) and of G^-1, Y (inverse operands).
+struct StepRaw {
+  int off[kOffs];
+  float2 gb[2], gi[2];
+};
+__device__ __forceinline__ void load_step(const int* sOff, const float2* sGV, int j, int e_fwd, int e_bwd,
+                                          bool with_gates, StepRaw& r) {
+#pragma unroll
+  for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
+  if (with_gates) {
+    r.gb[0] = sGV[64 * j + e_bwd];
+    r.gb[1] = sGV[64 * j + 16 + e_bwd];
+    r.gi[0] = sGV[64 * j + 32 + e_fwd];
+    r.gi[1] = sGV[64 * j + 48 + e_fwd];
+  }
+}
+
 // Padded LDS indices of the 4 amplitudes of group g (2*b_hi + b_lo order).
 __device__ __forceinline__ void group_index(const GateOff& o, int g, int (&ix)[4]) {
   int t = 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) t += bitsel(g, i, o.go[i]);
   ix[0] = t; ix[1] = t + o.ao[0]; ix[2] = t + o.ao[1]; ix[3] = t + o.ao[0] + o.ao[1];
+}
+__device__ __forceinline__ GateOff gate_offsets_raw(const int (&raw)[kOffs]) {
+  GateOff o;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) o.go[i] = __builtin_amdgcn_readfirstlane(raw[i]);
+  o.ao[0] = __builtin_amdgcn_readfirstlane(raw[8]);
+  o.ao[1] = __builtin_amdgcn_readfirstlane(raw[9]);
+  return o;
 }
 __device__ __forceinline__ GateOff gate_offsets(const int* sOff, int j) {
   GateOff o;
@@ -550,7 +597,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[wv][tid];
         a.ov_part[it * 4 + tid] = v;
       }
-    } else {
+    }
+    if (dstP != nullptr) {
       IO::read(st0, sP, tid);
       if (TANG) IO::read(st1, sD, tid);
       st_base = base;
@@ -562,6 +610,58 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   if (st_base >= 0) {
     IO::write(dstP, st0, st_base, xv, TS, tid);
     if (TANG) IO::write(dstD, st1, st_base, xv, TS, tid);
+  }
+}
+
+// Per-workgroup environment partials after the tile loop: sum the 4 waves' 16x16 MFMA blocks of
+// each gate slot (FP64, fixed order), then combine the real blocks into the 16 complex entries of
+// E = sum conj(a) psi^T and of D = sum conj(b) psi^T + conj(a) dpsi^T:
+// env_part[wg][j][0..32) = E (re, im interleaved, entry 4x + y), [32..64) = D.
+// sRed: kThreads * 4 doubles of LDS that the tile loop no longer uses.
+template <typename R, int MAXG>
+__device__ __forceinline__ void env_partials(typename Mfma<R>::acc_t (&acc)[MAXG], const double* sAcc, double* sRed,
+                                             double* sM, int ng, int tid, double* env_part) {
+  using M = Mfma<R>;
+  constexpr bool kF32 = std::is_same<R, float>::value;
+  const int wave = tid >> 6, lane = tid & 63, comp = lane & 15, sub = lane >> 4;
+#pragma unroll
+  for (int j = 0; j < MAXG; ++j) {
+    if (j < ng) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        sRed[(wave * 64 + lane) * 4 + r] = kF32 ? sAcc[(j * 4 + r) * kThreads + tid] : (double)acc[j][r];
+      __syncthreads();
+      if (wave == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          double v = 0;
+          for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[(wv * 64 + lane) * 4 + r];
+          sM[M::out_row(sub, r) * 16 + comp] = v;
+        }
+      }
+      __syncthreads();
+      if (tid < kEnvVals) {
+        const int which = tid >> 5, e = (tid >> 1) & 15, part = tid & 1;
+        const int ex = e >> 2, ey = e & 3;
+        // row of A component (st: 0 a, 1 b; ri: 0 re, 1 im; amplitude k), column of B (0 psi, 1 dpsi)
+#define RI(st, ri, k) (8 * (st) + 4 * (ri) + (k))
+#define P(r, c) sM[(r) * 16 + (c)]
+        double v;
+        if (which == 0) {
+          v = part == 0 ? P(RI(0, 0, ex), RI(0, 0, ey)) + P(RI(0, 1, ex), RI(0, 1, ey))
+                        : P(RI(0, 0, ex), RI(0, 1, ey)) - P(RI(0, 1, ex), RI(0, 0, ey));
+        } else {
+          v = part == 0 ? P(RI(1, 0, ex), RI(0, 0, ey)) + P(RI(1, 1, ex), RI(0, 1, ey)) +
+                              P(RI(0, 0, ex), RI(1, 0, ey)) + P(RI(0, 1, ex), RI(1, 1, ey))
+                        : P(RI(1, 0, ex), RI(0, 1, ey)) - P(RI(1, 1, ex), RI(0, 0, ey)) +
+                              P(RI(0, 0, ex), RI(1, 1, ey)) - P(RI(0, 1, ex), RI(1, 0, ey));
+        }
+#undef P
+#undef RI
+        env_part[((long long)blockIdx.x * kMaxGates + j) * kEnvVals + tid] = v;
+      }
+      __syncthreads();
+    }
   }
 }
 
@@ -862,47 +962,265 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
   }
 
-  // ---- per-workgroup environment partials: sum the 4 waves' 16x16 blocks, then combine
-  double* sRed = (double*)sY;   // kThreads * 4 doubles fit in sY for both precisions
-#pragma unroll
-  for (int j = 0; j < MAXG; ++j) {
-    if (j < ng) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        sRed[(wave * 64 + lane) * 4 + r] = kF32 ? sAcc[(j * 4 + r) * kThreads + tid] : (double)acc[j][r];
-      __syncthreads();
-      if (wave == 0) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          double v = 0;
-          for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[(wv * 64 + lane) * 4 + r];
-          sM[M::out_row(sub, r) * 16 + comp] = v;
-        }
-      }
-      __syncthreads();
-      if (tid < kEnvVals) {
-        const int which = tid >> 5, e = (tid >> 1) & 15, part = tid & 1;
-        const int ex = e >> 2, ey = e & 3;
-        // row of A component (st: 0 a, 1 b; ri: 0 re, 1 im; amplitude k), column of B (0 psi, 1 dpsi)
-#define RI(st, ri, k) (8 * (st) + 4 * (ri) + (k))
-#define P(r, c) sM[(r) * 16 + (c)]
-        double v;
-        if (which == 0) {
-          v = part == 0 ? P(RI(0, 0, ex), RI(0, 0, ey)) + P(RI(0, 1, ex), RI(0, 1, ey))
-                        : P(RI(0, 0, ex), RI(0, 1, ey)) - P(RI(0, 1, ex), RI(0, 0, ey));
-        } else {
-          v = part == 0 ? P(RI(1, 0, ex), RI(0, 0, ey)) + P(RI(1, 1, ex), RI(0, 1, ey)) +
-                              P(RI(0, 0, ex), RI(1, 0, ey)) + P(RI(0, 1, ex), RI(1, 1, ey))
-                        : P(RI(1, 0, ex), RI(0, 1, ey)) - P(RI(1, 1, ex), RI(0, 0, ey)) +
-                              P(RI(0, 0, ex), RI(1, 1, ey)) - P(RI(0, 1, ex), RI(1, 0, ey));
-        }
-#undef P
-#undef RI
-        a.env_part[((long long)blockIdx.x * kMaxGates + j) * kEnvVals + tid] = v;
-      }
-      __syncthreads();
+  env_partials<R, MAXG>(acc, sAcc, (double*)sY, sM, ng, tid, a.env_part);
+}
+
+// --------------------------------------------------------------------------------------------
+// Backward pass from the pass-output forward states (gates with a well-conditioned inverse)
+// --------------------------------------------------------------------------------------------
+// Instead of recomputing the forward states inside the tile from the pass input (and holding each
+// gate's operands until its environment is taken), this variant loads the forward states at the
+// pass OUTPUT and undoes every gate on them in the same step that undoes it on the backward states:
+// (psi, dpsi) <- (G^-1 psi, G^-1 dpsi + Y psi) with Y = -G^-1 V G^-1 (Eq. fis / Eq. dfis inverted).
+// The environment sums of gate k are then taken against its output states,
+//   Et = sum conj(a) psi_out^T,   Dt = sum conj(b) psi_out^T + conj(a) dpsi_out^T,
+// which the host maps to the input-side sums (psi_in = G^-1 psi_out, dpsi_in = G^-1 (dpsi_out -
+// V psi_in)): E = Et G^-T and D = (Dt - E V^T) G^-T.  Each step runs three independent products
+// (environment, W^dag on (a, b), W^-1 on (psi, dpsi)).  igates holds G^-1 | Y per gate (32 complex).
+template <typename R, bool TANG, int MAXG>
+__global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
+  using T = typename CT<R>::T;
+  using M = Mfma<R>;
+  using acc_t = typename M::acc_t;
+  using LD = Lds<T>;
+  using IO = TileIO<T>;
+  constexpr int TSMAX = LD::TSMAX, TSP = LD::TSP;
+  constexpr int NST = TANG ? 2 : 1;
+  constexpr bool kF32 = std::is_same<R, float>::value;
+  // sX: forward states (psi | dpsi) at the current gate's output, sY: backward states (a | b)
+  __shared__ __attribute__((aligned(16))) T sX[NST * TSP];
+  __shared__ __attribute__((aligned(16))) T sY[NST * TSP];
+  __shared__ double sM[16 * 16];
+  __shared__ double sAcc[kF32 ? MAXG * 4 * kThreads : 1];
+  __shared__ float2 sGV[kF32 ? kMaxGates * 64 : 1];   // per gate slot: G | V | G^-1 | Y
+  __shared__ int sOff[kMaxGates * kOffs];
+
+  const PassDesc& pd = a.pd;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int uwave = __builtin_amdgcn_readfirstlane(wave);
+  const int n = pd.n, mb = pd.mb, ng = pd.ng;
+  const int TS = 1 << mb, ngroups = TS >> 2;
+  const long long dim = 1LL << n;
+  const int tiles = 1 << (n - mb);
+  const long long items = (long long)a.n_samples * tiles;
+  const T* __restrict__ G = (const T*)a.gates;
+  const T* __restrict__ V = (const T*)a.dirs;
+  const T* __restrict__ GI = (const T*)a.igates;
+  const T* srcP = (const T*)a.src_psi;
+  const T* srcD = (const T*)a.src_dpsi;
+  T* abA = (T*)a.ab_a;
+  T* abB = (T*)a.ab_b;
+  const T* __restrict__ phi0 = (const T*)a.phi0;
+  const unsigned imask = (unsigned)pd.imask;
+  const bool wl = pd.wave_local != 0;
+  const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);
+  const int e_bwd = 4 * (lane >> 4) + ((lane >> 2) & 3);
+
+  if constexpr (kF32) {
+    for (int j = 0; j < ng; ++j) {
+      const int k = pd.gidx[j];
+      float2 v = make_float2(0.f, 0.f);
+      if (tid < 16) v = ((const float2*)G)[16 * k + tid];
+      else if (tid < 32) { if (TANG) v = ((const float2*)V)[16 * k + tid - 16]; }
+      else if (tid < 48) v = ((const float2*)GI)[32 * k + tid - 32];
+      else if (tid < 64) { if (TANG) v = ((const float2*)GI)[32 * k + tid - 32]; }
+      if (tid < 64) sGV[64 * j + tid] = v;
     }
   }
+  stage_offsets(pd, sOff, tid);
+
+  int xv[IO::NV];
+#pragma unroll
+  for (int v = 0; v < IO::NV; ++v) xv[v] = (int)deposit(IO::elem(tid, v), pd.abit, mb);
+
+  const int comp = lane & 15, sub = lane >> 4;
+  const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
+  const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSP + cri;  // in units of R
+
+  acc_t acc[MAXG];
+#pragma unroll
+  for (int j = 0; j < MAXG; ++j) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[j][r] = 0;
+  }
+  if constexpr (kF32) {
+    for (int i = tid; i < MAXG * 4 * kThreads; i += kThreads) sAcc[i] = 0;
+  }
+  for (int t = TS + tid; t < TSMAX; t += kThreads) {
+    sX[LD::at(t)] = cz<T>(); sY[LD::at(t)] = cz<T>();
+    if (TANG) { sX[TSP + LD::at(t)] = cz<T>(); sY[TSP + LD::at(t)] = cz<T>(); }
+  }
+  __syncthreads();
+
+  const long long it0 = items * blockIdx.x / gridDim.x;
+  const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
+  int s = 0;
+  unsigned x = 0;
+  if (it0 < it1) {
+    s = (int)(it0 / tiles);
+    x = (unsigned)deposit(it0 - (long long)s * tiles, pd.ibit, n - mb);
+  }
+
+  const bool common = !a.fold;
+  typename IO::V pfa[IO::NV], pfb[IO::NV], pfp[IO::NV], pfd[IO::NV];
+  if (common && it0 < it1) QHVP_BWD_PREFETCH(s, x);
+  typename IO::V st0[IO::NV], st1[IO::NV];
+  long long st_base = -1;
+
+  for (long long it = it0; it < it1; ++it) {
+    const long long base = (long long)s * dim + x;
+    const unsigned xn = next_tile(x, imask);
+    const int sn = s + (xn == 0u ? 1 : 0);
+
+    if (common) {
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v) {
+        const int sl = IO::slot(IO::elem(tid, v), TS);
+        *(typename IO::V*)(sY + sl) = pfa[v];
+        if (TANG) *(typename IO::V*)(sY + TSP + sl) = pfb[v];
+        *(typename IO::V*)(sX + sl) = pfp[v];
+        if (TANG) *(typename IO::V*)(sX + TSP + sl) = pfd[v];
+      }
+    } else {
+      // last pass: a = T_s phi0, b = Omega_s phi0 (the folded boundary); forward states from memory
+      T Ts, Os;
+      Ts.x = (R)a.tov[4 * s + 0]; Ts.y = (R)a.tov[4 * s + 1];
+      Os.x = (R)a.tov[4 * s + 2]; Os.y = (R)a.tov[4 * s + 3];
+      typename IO::V ph[IO::NV];
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v) ph[v] = *(const typename IO::V*)(phi0 + base + xv[v]);
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v)
+#pragma unroll
+        for (int e = 0; e < IO::EPV; ++e) {
+          const int t = IO::elem(tid, v) + e;
+          const int at = t < TS ? LD::at(t) : (1 << LD::PS) + e;
+          const T f = IO::part(ph[v], e);
+          sY[at] = cmul(Ts, f);
+          if (TANG) sY[TSP + at] = cmul(Os, f);
+        }
+      IO::load(sX, srcP, base, xv, TS, tid);
+      if (TANG) IO::load(sX + TSP, srcD, base, xv, TS, tid);
+    }
+    if (st_base >= 0) {
+      IO::write(abA, st0, st_base, xv, TS, tid);
+      if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+    }
+    __syncthreads();
+    if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
+
+    // complex64 with at most 4 gates: the step tables are loaded one step ahead (registers permitting)
+    constexpr bool kPipe = kF32 && MAXG <= kWaveLocalGates;
+    StepRaw nxt;
+    if (kPipe) load_step(sOff, sGV, ng - 1, e_fwd, e_bwd, true, nxt);
+#pragma unroll
+    for (int j = MAXG - 1; j >= 0; --j) {
+      if (j < ng) {
+        StepRaw cur;
+        if (kPipe) {
+          cur = nxt;
+          if (j > 0) load_step(sOff, sGV, j - 1, e_fwd, e_bwd, true, nxt);
+        } else {
+          load_step(sOff, sGV, j, e_fwd, e_bwd, kF32, cur);
+        }
+        const GateOff O = gate_offsets_raw(cur.off);
+        const int* go = O.go;
+        const int* ao = O.ao;
+        const int tl = bitsel(sub, 0, go[0]) + bitsel(sub, 1, go[1]) + bitsel(cidx, 0, ao[0]) +
+                       bitsel(cidx, 1, ao[1]) + bitsel(uwave, 0, go[6]) + bitsel(uwave, 1, go[7]);
+        const R* ys = (const R*)sY + lane_scalar_off + 2 * tl;
+        const R* xs = (const R*)sX + lane_scalar_off + 2 * tl;
+        const bool undo_ab = j > 0 || a.store_ab;   // (a, b) at the pass input are needed
+        R av[16], bx[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int uo = ((c & 1) ? go[2] : 0) + ((c & 2) ? go[3] : 0) + ((c & 4) ? go[4] : 0) + ((c & 8) ? go[5] : 0);
+          av[c] = ys[2 * uo];
+          bx[c] = xs[2 * uo];
+        }
+        if constexpr (kF32) {
+          int tw, ch[4];
+          w_offsets(O, uwave, lane, tw, ch);
+          WTile<TANG> wy, wx;
+          if (undo_ab) wy.load(sY, sY + TSP, tw, ch);
+          if (j > 0) wx.load(sX, sX + TSP, tw, ch);
+          pin16(av);
+          pin16(bx);
+          if (undo_ab) wy.pin();
+          if (j > 0) wx.pin();
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bx[c], acc[j]);
+          if (undo_ab) {
+            wy.mfma(w_operands_xy(cur.gb[0], cur.gb[1], true, lane));
+            wy.store(sY, sY + TSP, tw, ch);
+          }
+          if (j > 0) {
+            wx.mfma(w_operands_xy(cur.gi[0], cur.gi[1], false, lane));
+            wx.store(sX, sX + TSP, tw, ch);
+          }
+        } else {
+          pin16(av);
+          pin16(bx);
+#pragma unroll
+          for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bx[c], acc[j]);
+          const auto Gk = opaque(G + 16 * pd.gidx[j]);
+          const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
+          const auto GIk = opaque(GI + 32 * pd.gidx[j]);
+          const auto YIk = opaque(GI + 32 * pd.gidx[j] + 16);
+          if (tid < ngroups) {
+            int ix[4];
+            group_index(O, tid, ix);
+            if (undo_ab) {
+              T pa[4], pb[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSP + ix[i]]; }
+              apply_wdag<T, TANG>(Gk, Vk, pa, pb);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
+            }
+            if (j > 0) {
+              T p[4], d[4];
+#pragma unroll
+              for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
+              apply_w<T, TANG>(GIk, YIk, p, d);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSP + ix[i]] = d[i]; }
+            }
+          }
+        }
+        if (wl && j > 0) wave_sync();
+        else __syncthreads();
+      }
+    }
+
+    if constexpr (kF32) {
+#pragma unroll
+      for (int j = 0; j < MAXG; ++j) {
+        if (j < ng) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            sAcc[(j * 4 + r) * kThreads + tid] += (double)acc[j][r];
+            acc[j][r] = 0;
+          }
+        }
+      }
+    }
+
+    if (a.store_ab) {
+      IO::read(st0, sY, tid);
+      if (TANG) IO::read(st1, sY + TSP, tid);
+      st_base = base;
+    }
+    __syncthreads();
+    s = sn;
+    x = xn;
+  }
+  if (st_base >= 0) {
+    IO::write(abA, st0, st_base, xv, TS, tid);
+    if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+  }
+  env_partials<R, MAXG>(acc, sAcc, (double*)sY, sM, ng, tid, a.env_part);
 }
 
 #undef QHVP_FWD_PREFETCH
@@ -955,7 +1273,7 @@ namespace {
 // persistent kernels split their tiles evenly over the grid, so a grid of exactly this many
 // workgroups runs in one round instead of leaving a partial second round.
 int resident_wgs(const void* kern, int slot) {
-  static int cache[16][16] = {};
+  static int cache[16][32] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 2048;
   int& c = cache[dev][slot];
@@ -999,9 +1317,21 @@ int fwd_grid(Prec prec, int tangent, long long items) {
   return pick_grid(items, resident_wgs(k, slot));
 }
 
-int bwd_grid(Prec prec, int tangent, int ng, long long items) {
+template <int MAXG>
+const void* bwd_out_kernel_g(Prec prec, int tangent) {
+  if (prec == P_C64) return tangent ? (const void*)k_bwd_out<float, true, MAXG> : (const void*)k_bwd_out<float, false, MAXG>;
+  return tangent ? (const void*)k_bwd_out<double, true, MAXG> : (const void*)k_bwd_out<double, false, MAXG>;
+}
+
+const void* bwd_out_kernel(Prec prec, int tangent, int ng, int* slot) {
+  const bool small = ng <= kWaveLocalGates;
+  *slot = 12 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0) + (small ? 4 : 0);
+  return small ? bwd_out_kernel_g<kWaveLocalGates>(prec, tangent) : bwd_out_kernel_g<kMaxGates>(prec, tangent);
+}
+
+int bwd_grid(Prec prec, int tangent, int ng, long long items, int from_output) {
   int slot;
-  const void* k = bwd_kernel(prec, tangent, ng, &slot);
+  const void* k = from_output ? bwd_out_kernel(prec, tangent, ng, &slot) : bwd_kernel(prec, tangent, ng, &slot);
   return pick_grid(items, resident_wgs(k, slot));
 }
 
@@ -1023,6 +1353,15 @@ int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
   const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
   int slot;
   const void* k = bwd_kernel(prec, a.tangent, a.pd.ng, &slot);
+  dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
+  void* args[] = {(void*)&a};
+  return (int)hipLaunchKernel(k, grid, block, args, 0, (hipStream_t)stream);
+}
+
+int launch_bwd_out(Prec prec, const BwdArgs& a, void* stream) {
+  const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
+  int slot;
+  const void* k = bwd_out_kernel(prec, a.tangent, a.pd.ng, &slot);
   dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
   void* args[] = {(void*)&a};
   return (int)hipLaunchKernel(k, grid, block, args, 0, (hipStream_t)stream);

@@ -113,6 +113,30 @@ def test_non_unitary_point_and_general_direction(gpu):
     _check(gp, ref, "c128", G, V, "nonunitary")
 
 
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+@pytest.mark.parametrize("kind", ["unitary", "near_unitary", "ill_conditioned"])
+def test_backward_algorithms(gpu, monkeypatch, precision, kind):
+    """The backward sweep from pass outputs (undoing gates with G^-1, environments mapped back on the
+    host) and the recomputing sweep both match the oracle; near-unitary gates make G^-1 differ from
+    G^dag, and gates far from unitary must fall back to recomputation."""
+    p = make_problem(11, 4, 3, seed=66)
+    rng = np.random.default_rng(6)
+    noise = rng.standard_normal(p.G.shape) + 1j * rng.standard_normal(p.G.shape)
+    G = {"unitary": p.G, "near_unitary": p.G + 0.05 * noise, "ill_conditioned": p.G + 2.0 * noise}[kind]
+    V = p.V
+    psi, phi = circuit.labels(p.uref, p.samples, p.n, p.L_ref)
+    ref = sv.evaluate(psi, phi, G, V, p.n, p.L)
+    gp = _gpu_problem(p, precision)
+    monkeypatch.setenv("QHVP_BACKWARD", "recompute")
+    g_r, h_r = _check(gp, ref, precision, G, V, kind + " recompute")
+    assert not gp.backward_from_outputs
+    monkeypatch.delenv("QHVP_BACKWARD")
+    g_i, h_i = _check(gp, ref, precision, G, V, kind + " auto")
+    assert gp.backward_from_outputs == (kind != "ill_conditioned")
+    tol = TOL[precision]
+    assert _rel(g_i, g_r) <= tol and _rel(h_i, h_r) <= tol
+
+
 def test_riemannian_outputs(gpu):
     p = make_problem(8, 5, 4, seed=66)
     rng = np.random.default_rng(6)
