@@ -125,10 +125,33 @@ std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* layer_f
   return passes;
 }
 
-// Padded LDS index of tile element t in the kernels' layout (16 spare bytes after every 256 bytes).
+// LDS index of tile element t in the kernels' layout: complex64 per-bit offsets (kLdsPadC64),
+// complex128 16 spare bytes after every 256 bytes.
 int lds_at(int t, int elem_bytes) {
-  const int ps = elem_bytes == 8 ? 5 : 4;   // log2(elements per 256 bytes)
-  return t + (t >> ps) * (16 / elem_bytes);
+  if (elem_bytes == 8) {
+    int r = t;
+    for (int b = 5; b < qhvp::kMaxTileBits; ++b) r += ((t >> b) & 1) * qhvp::kLdsPadC64[b];
+    return r;
+  }
+  return t + (t >> 4);
+}
+
+// 2-adic valuation of x mod 32 (5 for x = 0 mod 32).  Five offsets whose valuations are 0..4 give
+// 32 distinct subset sums mod 32, i.e. distinct banks for the lanes they index.
+int val32(int x) {
+  x &= 31;
+  if (x == 0) return 5;
+  int v = 0;
+  while (!(x & 1)) { x >>= 1; ++v; }
+  return v;
+}
+bool spans32(int a, int b, int c, int d, int e) {
+  int seen = 0;
+  for (int v : {val32(a), val32(b), val32(c), val32(d), val32(e)}) {
+    if (v == 5 || (seen >> v & 1)) return false;
+    seen |= 1 << v;
+  }
+  return true;
 }
 
 // Per-pass constants of the kernels' tile addressing: the tile-enumeration mask and, per gate, the
@@ -155,9 +178,34 @@ void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
       const int lo = pd.tlo[j], hi = pd.thi[j];
       int pos[8];
       if (pd.wave_local) {
-        int k = 0;
+        int avail[6], k = 0;
         for (int b = 0; b < qhvp::kMaxTileBits; ++b)
-          if (b != lo && b != hi && b != f0 && b != f1) pos[k++] = b;
+          if (b != lo && b != hi && b != f0 && b != f1) avail[k++] = b;
+        for (int i = 0; i < 6; ++i) pos[i] = avail[i];
+        if (elem_bytes == 8) {
+          // complex64: choose the group bits the lanes run over (bits 0..3: the 16 columns of the
+          // gate application, bits 0..1: the sub-rows of the environment operands) so that both
+          // access patterns hit distinct banks: gate application over {bits 0..3, tlo}, environment
+          // over {tlo, thi, second state array, bits 0..1}
+          auto O = [&](int b) { return lds_at(1 << b, elem_bytes); };
+          int best = -1;
+          for (int a0 = 0; a0 < 6 && best < 2; ++a0)
+            for (int a1 = 0; a1 < 6 && best < 2; ++a1)
+              for (int a2 = 0; a2 < 6 && best < 2; ++a2)
+                for (int a3 = 0; a3 < 6 && best < 2; ++a3) {
+                  if (a0 == a1 || a0 == a2 || a0 == a3 || a1 == a2 || a1 == a3 || a2 == a3) continue;
+                  const int p0 = avail[a0], p1 = avail[a1], p2 = avail[a2], p3 = avail[a3];
+                  const int score = (spans32(O(lo), O(hi), qhvp::kTspC64, O(p0), O(p1)) ? 1 : 0) +
+                                    (spans32(O(p0), O(p1), O(p2), O(p3), O(lo)) ? 1 : 0);
+                  if (score > best) {
+                    best = score;
+                    pos[0] = p0; pos[1] = p1; pos[2] = p2; pos[3] = p3;
+                    int r = 4;
+                    for (int i = 0; i < 6; ++i)
+                      if (i != a0 && i != a1 && i != a2 && i != a3) pos[r++] = avail[i];
+                  }
+                }
+        }
         pos[6] = f0;
         pos[7] = f1;
       } else {

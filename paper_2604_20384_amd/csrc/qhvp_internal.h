@@ -19,6 +19,15 @@ constexpr int kMaxQubits = 30;
 constexpr int kThreads = 256;     // 4 wave64s; one 4-amplitude group per thread per gate at mb = 10
 constexpr int kEnvVals = 64;      // 16 complex E + 16 complex D per gate, as 64 doubles
 
+// complex64 LDS tile layout (8-byte elements; gfx950 LDS: 64 banks of 4 bytes): tile element t sits
+// at t + sum of kLdsPadC64[b] over the set bits b of t, i.e. tile bit b at element offset
+// 2^b + kLdsPadC64[b] = 1, 2, 4, 8, 16, 33, 68, 136, 272, 552.  The offsets' residues mod 32 let the
+// kernels' lane patterns (16 lanes over 4 group bits plus a gate bit; 32 lanes over two gate bits,
+// two group bits and the second state array) hit distinct banks for almost every gate.  Each state
+// array spans kTspC64 elements (the extent 1093, rounded to a residue of the same class).
+constexpr int kLdsPadC64[kMaxTileBits] = {0, 0, 0, 0, 0, 1, 4, 8, 16, 40};
+constexpr int kTspC64 = 1094;
+
 struct PassDesc {
   int n;      // qubits
   int mb;     // tile bits

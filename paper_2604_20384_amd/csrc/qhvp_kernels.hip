@@ -156,17 +156,30 @@ __device__ __forceinline__ void apply_wdag(cptr<decltype(T::x)> G, cptr<decltype
 }
 
 
-// Padded LDS index of tile element t: 16 spare bytes after every 256-byte row, so that the
-// power-of-two strides of gates on low tile bits spread over the banks while 16-byte vector
-// accesses stay aligned.  Additive over index values with disjoint bits (used to split MFMA
-// operand addresses into a per-lane and a wave-uniform part).
-template <typename T> struct Lds {
-  static constexpr int PS = sizeof(T) == 8 ? 5 : 4;                      // log2(elements per 256 B)
-  static constexpr int PAD = 16 / (int)sizeof(T);                        // elements of padding per row
+// LDS index of tile element t.  Both layouts are additive over index values with disjoint bits
+// (used to split MFMA operand addresses into a per-lane and a wave-uniform part), and leave index
+// DUMMY unused (a sink for writes of elements beyond a tile of fewer than 2^kMaxTileBits).
+template <typename T> struct Lds;
+// complex64: per-bit offsets chosen against the 64 banks (kLdsPadC64); TSP elements per state array.
+template <> struct Lds<float2> {
   static constexpr int TSMAX = 1 << kMaxTileBits;
-  // padded size of one state array, +32 bytes so that a second state array starts 8 banks over
-  static constexpr int TSP = TSMAX + (TSMAX >> PS) * PAD + 32 / (int)sizeof(T);
-  static __device__ __forceinline__ int at(int t) { return t + (t >> PS) * PAD; }
+  static constexpr int TSP = kTspC64;
+  static constexpr int DUMMY = 32;
+  static __device__ __forceinline__ int at(int t) {
+    int r = t;
+#pragma unroll
+    for (int b = 5; b < kMaxTileBits; ++b) r += ((t >> b) & 1) * kLdsPadC64[b];
+    return r;
+  }
+};
+// complex128: 16 spare bytes after every 256-byte row (+32 bytes so that the second state array
+// starts 8 banks over).
+template <> struct Lds<double2> {
+  static constexpr int PS = 4;   // log2(elements per 256 B)
+  static constexpr int TSMAX = 1 << kMaxTileBits;
+  static constexpr int TSP = TSMAX + (TSMAX >> PS) + 2;
+  static constexpr int DUMMY = 1 << PS;
+  static __device__ __forceinline__ int at(int t) { return t + (t >> PS); }
 };
 
 // Global <-> LDS transfer of one state of a tile in 16-byte vectors: thread tid moves tile
@@ -183,20 +196,42 @@ template <typename T> struct TileIO {
   static constexpr int EPV = 16 / (int)sizeof(T);
   static constexpr int NV = (1 << kMaxTileBits) / EPV / kThreads;
   static __device__ __forceinline__ int elem(int tid, int v) { return EPV * (tid + kThreads * v); }
-  // LDS slot of tile element t, or for t >= TS the (never read) padding slot after row 0; the
-  // write is then unconditional, which keeps the loads from being sunk into guarded blocks.
-  static __device__ __forceinline__ int slot(int t, int TS) { return t < TS ? Lds<T>::at(t) : (1 << Lds<T>::PS); }
+  // LDS slot of tile element t, or for t >= TS the (never read) dummy slot; the write is then
+  // unconditional, which keeps the loads from being sunk into guarded blocks.
+  static __device__ __forceinline__ int slot(int t, int TS) { return t < TS ? Lds<T>::at(t) : Lds<T>::DUMMY; }
+  static __device__ __forceinline__ T part(const V& r, int e) {
+    T o;
+    if constexpr (sizeof(T) == 8) { o.x = e ? r[2] : r[0]; o.y = e ? r[3] : r[1]; }
+    else { o.x = r[0]; o.y = r[1]; }
+    return o;
+  }
+  // element-wise LDS access of one 16-byte vector (complex64 elements need not be 16-byte aligned)
+  static __device__ __forceinline__ void put(T* lds, int t, int TS, const V& r) {
+#pragma unroll
+    for (int e = 0; e < EPV; ++e) lds[slot(t + e, TS)] = part(r, e);
+  }
+  static __device__ __forceinline__ V get(const T* lds, int t) {
+    V r;
+    if constexpr (sizeof(T) == 8) {
+      const T a = lds[Lds<T>::at(t)], b = lds[Lds<T>::at(t + 1)];
+      r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y;
+    } else {
+      const T a = lds[Lds<T>::at(t)];
+      r[0] = a.x; r[1] = a.y;
+    }
+    return r;
+  }
   static __device__ __forceinline__ void load(T* lds, const T* g, long long base, const int* xv, int TS, int tid) {
     V r[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) r[v] = *(const V*)(g + base + xv[v]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) *(V*)(lds + slot(elem(tid, v), TS)) = r[v];
+    for (int v = 0; v < NV; ++v) put(lds, elem(tid, v), TS, r[v]);
   }
   static __device__ __forceinline__ void store(T* g, const T* lds, long long base, const int* xv, int TS, int tid) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      const V r = *(const V*)(lds + Lds<T>::at(elem(tid, v)));
+      const V r = get(lds, elem(tid, v));
       if (elem(tid, v) < TS) *(V*)(g + base + xv[v]) = r;
     }
   }
@@ -204,18 +239,12 @@ template <typename T> struct TileIO {
   // stores can be issued after the next tile's loads have been waited for.
   static __device__ __forceinline__ void read(V (&r)[NV], const T* lds, int tid) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) r[v] = *(const V*)(lds + Lds<T>::at(elem(tid, v)));
+    for (int v = 0; v < NV; ++v) r[v] = get(lds, elem(tid, v));
   }
   static __device__ __forceinline__ void write(T* g, const V (&r)[NV], long long base, const int* xv, int TS, int tid) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       if (elem(tid, v) < TS) *(V*)(g + base + xv[v]) = r[v];
-  }
-  static __device__ __forceinline__ T part(const V& r, int e) {
-    T o;
-    if constexpr (sizeof(T) == 8) { o.x = e ? r[2] : r[0]; o.y = e ? r[3] : r[1]; }
-    else { o.x = r[0]; o.y = r[1]; }
-    return o;
   }
 };
 
@@ -522,9 +551,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
     } else {
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v) {
-        const int sl = IO::slot(IO::elem(tid, v), TS);
-        *(typename IO::V*)(sP + sl) = pf0[v];
-        if (TANG) *(typename IO::V*)(sD + sl) = pf1[v];
+        IO::put(sP, IO::elem(tid, v), TS, pf0[v]);
+        if (TANG) IO::put(sD, IO::elem(tid, v), TS, pf1[v]);
       }
     }
     if (st_base >= 0) {
@@ -785,11 +813,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     if (common) {
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v) {
-        const int sl = IO::slot(IO::elem(tid, v), TS);
-        *(typename IO::V*)(sY + sl) = pfa[v];
-        if (TANG) *(typename IO::V*)(sY + TSP + sl) = pfb[v];
-        *(typename IO::V*)(sX + sl) = pfp[v];
-        if (TANG) *(typename IO::V*)(sX + TSP + sl) = pfd[v];
+        IO::put(sY, IO::elem(tid, v), TS, pfa[v]);
+        if (TANG) IO::put(sY + TSP, IO::elem(tid, v), TS, pfb[v]);
+        IO::put(sX, IO::elem(tid, v), TS, pfp[v]);
+        if (TANG) IO::put(sX + TSP, IO::elem(tid, v), TS, pfd[v]);
       }
     } else {
     // ---- backward states (a, b) at the pass output
@@ -805,7 +832,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 #pragma unroll
         for (int e = 0; e < IO::EPV; ++e) {
           const int t = IO::elem(tid, v) + e;
-          const int at = t < TS ? LD::at(t) : (1 << LD::PS) + e;    // padding slot when outside the tile
+          const int at = t < TS ? LD::at(t) : LD::DUMMY;    // dummy slot when outside the tile
           const T f = IO::part(ph[v], e);
           sY[at] = cmul(Ts, f);
           if (TANG) sY[TSP + at] = cmul(Os, f);
@@ -1076,11 +1103,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     if (common) {
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v) {
-        const int sl = IO::slot(IO::elem(tid, v), TS);
-        *(typename IO::V*)(sY + sl) = pfa[v];
-        if (TANG) *(typename IO::V*)(sY + TSP + sl) = pfb[v];
-        *(typename IO::V*)(sX + sl) = pfp[v];
-        if (TANG) *(typename IO::V*)(sX + TSP + sl) = pfd[v];
+        IO::put(sY, IO::elem(tid, v), TS, pfa[v]);
+        if (TANG) IO::put(sY + TSP, IO::elem(tid, v), TS, pfb[v]);
+        IO::put(sX, IO::elem(tid, v), TS, pfp[v]);
+        if (TANG) IO::put(sX + TSP, IO::elem(tid, v), TS, pfd[v]);
       }
     } else {
       // last pass: a = T_s phi0, b = Omega_s phi0 (the folded boundary); forward states from memory
@@ -1095,7 +1121,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
 #pragma unroll
         for (int e = 0; e < IO::EPV; ++e) {
           const int t = IO::elem(tid, v) + e;
-          const int at = t < TS ? LD::at(t) : (1 << LD::PS) + e;
+          const int at = t < TS ? LD::at(t) : LD::DUMMY;
           const T f = IO::part(ph[v], e);
           sY[at] = cmul(Ts, f);
           if (TANG) sY[TSP + at] = cmul(Os, f);
