@@ -100,7 +100,7 @@ def measured_traffic(kernel_name):
     summary (scaled by the copy-kernel calibration), or None if the kernel source has changed
     since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic_k_bwd_c64.json")
+    path = os.path.join(ROOT, "profiles", "traffic_k_bwd_out_c64.json")
     src = os.path.join(ROOT, "paper_2604_20384_amd", "csrc", "qhvp_kernels.hip")
     try:
         rec = json.load(open(path))
