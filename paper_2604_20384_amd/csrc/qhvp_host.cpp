@@ -48,80 +48,100 @@ int num_gates(int n, int L) {
   return ((L + 1) / 2) * (n / 2) + (L / 2) * ((n - 1) / 2);
 }
 
-// One brickwall layer -> passes.  Gates on qubits (q, q+1) touch statevector bits
-// lo = n-2-q and lo+1.  Greedy in increasing lo: the tile keeps the low
-// kCoalesceBits bits and adds each gate's two bits while it has room; the leftover
-// room is filled with the lowest unused bits (longer contiguous runs).
-void plan_layer_cap(int n, int layer, int first_gate, int cap, std::vector<qhvp::PassDesc>& out) {
-  const int mbmax = std::min(n, qhvp::kMaxTileBits);
-  std::vector<int> qs;
-  for (int q = layer % 2; q + 1 < n; q += 2) qs.push_back(q);
-  // gate index of pair q in this layer
-  std::vector<std::pair<int, int>> gl;  // (lo bit, gate index)
-  for (size_t i = 0; i < qs.size(); ++i) gl.push_back({n - 2 - qs[i], first_gate + (int)i});
-  std::sort(gl.begin(), gl.end());
-  const int cb = std::min(kCoalesceBits, mbmax);
-  size_t i = 0;
-  while (i < gl.size()) {
-    std::vector<bool> act(n, false);
-    for (int b = 0; b < cb; ++b) act[b] = true;
-    int cnt = cb;
-    std::vector<int> gates;
-    while (i < gl.size() && (int)gates.size() < cap) {
-      int lo = gl[i].first;
-      int add = (act[lo] ? 0 : 1) + (act[lo + 1] ? 0 : 1);
-      if (cnt + add > mbmax) break;
-      act[lo] = act[lo + 1] = true;
-      cnt += add;
-      gates.push_back(i);
-      ++i;
+// Circuit -> passes.  Gate k of the brickwall (layers in order, qubits q = l%2, l%2+2, ... within
+// layer l) acts on statevector bits lo = n-2-q and lo+1 and must follow the gates of layer l-1 on
+// bits lo-1..lo+1.  A pass applies up to kMaxGates gates, in an order that respects these
+// dependencies, to tiles spanned by 2^mb index bits: the low kCoalesceBits bits (runs of >= 16
+// amplitudes per global access) plus a window of mb - kCoalesceBits consecutive bits.  The planner
+// is greedy: each pass takes the window that admits the most gates (scanning gates in index order,
+// so a gate may join once the gates it follows are done or already in the pass), and - at full
+// tile size - at most mb - 2 touched tile bits, so that two untouched bits index the waves and the
+// pass runs without workgroup barriers (wave-local).  Gates of several layers share a pass, which
+// cuts the number of HBM round trips (n=20, L=20: 40 passes for 190 gates; one layer per pass
+// would need 60).  gates_before[q] = gates in the passes before q (np + 1 entries).
+std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* gates_before) {
+  const int K = num_gates(n, L);
+  std::vector<int> glo(K), glayer(K);
+  std::vector<std::vector<int>> at(L, std::vector<int>(n, -1));   // at[l][lo] = gate index
+  for (int l = 0, k = 0; l < L; ++l)
+    for (int q = l % 2; q + 1 < n; q += 2, ++k) {
+      glo[k] = n - 2 - q;
+      glayer[k] = l;
+      at[l][glo[k]] = k;
     }
-    for (int b = 0; b < n && cnt < mbmax; ++b)
-      if (!act[b]) { act[b] = true; ++cnt; }
+  std::vector<std::vector<int>> deps(K);
+  for (int k = 0; k < K; ++k)
+    if (glayer[k] > 0)
+      for (int b = glo[k] - 1; b <= glo[k] + 1; ++b)
+        if (b >= 0 && b < n && at[glayer[k] - 1][b] >= 0) deps[k].push_back(at[glayer[k] - 1][b]);
+
+  const int mb = std::min(n, qhvp::kMaxTileBits);
+  const int cb = std::min(kCoalesceBits, mb);
+  std::vector<std::vector<int>> cands;   // tile bits of each candidate, ascending
+  if (n <= mb) {
+    std::vector<int> all(n);
+    for (int b = 0; b < n; ++b) all[b] = b;
+    cands.push_back(all);
+  } else {
+    for (int w = cb; w + (mb - cb) <= n; ++w) {
+      std::vector<int> t;
+      for (int b = 0; b < cb; ++b) t.push_back(b);
+      for (int b = w; b < w + mb - cb; ++b) t.push_back(b);
+      cands.push_back(t);
+    }
+  }
+  const int max_touched = mb == qhvp::kMaxTileBits ? mb - 2 : mb;
+
+  std::vector<qhvp::PassDesc> passes;
+  std::vector<char> done(K, 0), in_pass(K, 0);
+  if (gates_before) gates_before->assign(1, 0);
+  int remaining = K, total = 0;
+  while (remaining > 0) {
+    std::vector<int> best, best_bits;
+    for (const auto& bits : cands) {
+      std::vector<char> in_tile(n, 0), touched(n, 0);
+      for (int b : bits) in_tile[b] = 1;
+      std::vector<int> take;
+      int nt = 0;
+      for (int k = 0; k < K && (int)take.size() < qhvp::kMaxGates; ++k) {
+        if (done[k] || !in_tile[glo[k]] || !in_tile[glo[k] + 1]) continue;
+        bool ready = true;
+        for (int d : deps[k]) ready = ready && (done[d] || in_pass[d]);
+        if (!ready) continue;
+        const int add = (touched[glo[k]] ? 0 : 1) + (touched[glo[k] + 1] ? 0 : 1);
+        if (nt + add > max_touched) continue;
+        touched[glo[k]] = touched[glo[k] + 1] = 1;
+        nt += add;
+        in_pass[k] = 1;
+        take.push_back(k);
+      }
+      for (int k : take) in_pass[k] = 0;
+      if (take.size() > best.size()) { best = take; best_bits = bits; }
+    }
     qhvp::PassDesc pd;
     std::memset(&pd, 0, sizeof(pd));
     pd.n = n;
-    pd.mb = cnt;
-    int ti = 0, ii = 0;
+    pd.mb = (int)best_bits.size();
     std::vector<int> tpos(n, -1);
-    for (int b = 0; b < n; ++b) {
+    std::vector<char> act(n, 0);
+    for (int b : best_bits) act[b] = 1;
+    for (int b = 0, ti = 0, ii = 0; b < n; ++b) {
       if (act[b]) { pd.abit[ti] = b; tpos[b] = ti++; }
       else pd.ibit[ii++] = b;
     }
-    // gates keep their layer order (by increasing q, i.e. decreasing lo); they commute anyway
-    std::sort(gates.begin(), gates.end(), [&](int x, int y) { return gl[x].second < gl[y].second; });
-    pd.ng = (int)gates.size();
+    pd.ng = (int)best.size();
     for (int g = 0; g < pd.ng; ++g) {
-      int lo = gl[gates[g]].first;
-      pd.gidx[g] = gl[gates[g]].second;
-      pd.tlo[g] = tpos[lo];
-      pd.thi[g] = tpos[lo + 1];
+      const int k = best[g];
+      pd.gidx[g] = k;
+      pd.tlo[g] = tpos[glo[k]];
+      pd.thi[g] = tpos[glo[k] + 1];
+      done[k] = 1;
     }
-    out.push_back(pd);
+    remaining -= pd.ng;
+    total += pd.ng;
+    passes.push_back(pd);
+    if (gates_before) gates_before->push_back(total);
   }
-}
-
-// Passes of at most kWaveLocalGates gates leave two tile bits untouched at mb = kMaxTileBits, which
-// the kernels use to give each wave its own quarter of the tile (no workgroup barrier between the
-// gates).  Take that cap whenever it needs no more passes than the full kMaxGates.
-void plan_layer(int n, int layer, int first_gate, std::vector<qhvp::PassDesc>& out) {
-  std::vector<qhvp::PassDesc> small, full;
-  plan_layer_cap(n, layer, first_gate, qhvp::kWaveLocalGates, small);
-  plan_layer_cap(n, layer, first_gate, qhvp::kMaxGates, full);
-  const auto& best = small.size() <= full.size() ? small : full;
-  out.insert(out.end(), best.begin(), best.end());
-}
-
-std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* layer_first_pass) {
-  std::vector<qhvp::PassDesc> passes;
-  int k = 0;
-  for (int l = 0; l < L; ++l) {
-    if (layer_first_pass) layer_first_pass->push_back((int)passes.size());
-    size_t before = passes.size();
-    plan_layer(n, l, k, passes);
-    for (size_t p = before; p < passes.size(); ++p) k += passes[p].ng;
-  }
-  if (layer_first_pass) layer_first_pass->push_back((int)passes.size());
   return passes;
 }
 
@@ -224,15 +244,23 @@ void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
 // Segments of the backward sweep (pass index ranges); each segment starts at a stored
 // checkpoint (pass 0's input is regenerated from the samples).
 std::vector<std::pair<int, int>> plan_segments(int n, int L, int ckpt_every) {
-  std::vector<int> lfp;
-  auto passes = plan_circuit(n, L, &lfp);
+  std::vector<int> gb;
+  auto passes = plan_circuit(n, L, &gb);
   const int np = (int)passes.size();
   std::vector<std::pair<int, int>> seg;
   if (ckpt_every > 0) {
-    for (int l = 0; l < L; l += ckpt_every) {
-      int l1 = std::min(L, l + ckpt_every);
-      if (lfp[l1] > lfp[l]) seg.push_back({lfp[l], lfp[l1]});   // layers without gates (n = 2) add no segment
-    }
+    // a checkpoint about every ckpt_every layers' worth of gates: a segment ends before the first
+    // pass that starts at or beyond the next multiple of ckpt_every * K / L gates
+    const double step = (double)ckpt_every * num_gates(n, L) / L;
+    double next = step;
+    int start = 0;
+    for (int q = 1; q < np; ++q)
+      if (gb[q] >= next - 1e-9) {
+        seg.push_back({start, q});
+        start = q;
+        while (next <= gb[q] + 1e-9) next += step;
+      }
+    seg.push_back({start, np});
   } else {
     int c = ckpt_every == 0 ? 1 : -ckpt_every;
     for (int p = 0; p < np; p += c) seg.push_back({p, std::min(np, p + c)});

@@ -13,7 +13,7 @@ namespace qhvp {
 // bits are always active so that global loads and stores touch contiguous
 // runs.  The remaining (inactive) bits ibit[0..n-mb) enumerate the tiles.
 constexpr int kMaxGates = 5;
-constexpr int kWaveLocalGates = 4;   // passes of at most this many gates can run wave-local
+constexpr int kSmallMaxGates = 4;   // passes of at most this many gates use a lighter kernel instance
 constexpr int kMaxTileBits = 10;
 constexpr int kMaxQubits = 30;
 constexpr int kThreads = 256;     // 4 wave64s; one 4-amplitude group per thread per gate at mb = 10

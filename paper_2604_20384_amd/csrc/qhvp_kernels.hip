@@ -800,7 +800,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   if (common && it0 < it1) QHVP_BWD_PREFETCH(s, x);
   // deferred stores of the previous tile's (a, b), as in k_fwd (not with 5-gate passes, where the
   // registers they hold would halve the occupancy)
-  constexpr bool kDefer = MAXG <= kWaveLocalGates;
+  constexpr bool kDefer = MAXG <= kSmallMaxGates;
   typename IO::V st0[IO::NV], st1[IO::NV];
   long long st_base = -1;
 
@@ -1137,7 +1137,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
 
     // complex64 with at most 4 gates: the step tables are loaded one step ahead (registers permitting)
-    constexpr bool kPipe = kF32 && MAXG <= kWaveLocalGates;
+    constexpr bool kPipe = kF32 && MAXG <= kSmallMaxGates;
     StepRaw nxt;
     if (kPipe) load_step(sOff, sGV, ng - 1, e_fwd, e_bwd, true, nxt);
 #pragma unroll
@@ -1331,9 +1331,9 @@ const void* bwd_kernel_g(Prec prec, int tangent) {
 }
 
 const void* bwd_kernel(Prec prec, int tangent, int ng, int* slot) {
-  const bool small = ng <= kWaveLocalGates;
+  const bool small = ng <= kSmallMaxGates;
   *slot = 4 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0) + (small ? 4 : 0);
-  return small ? bwd_kernel_g<kWaveLocalGates>(prec, tangent) : bwd_kernel_g<kMaxGates>(prec, tangent);
+  return small ? bwd_kernel_g<kSmallMaxGates>(prec, tangent) : bwd_kernel_g<kMaxGates>(prec, tangent);
 }
 }  // namespace
 
@@ -1350,9 +1350,9 @@ const void* bwd_out_kernel_g(Prec prec, int tangent) {
 }
 
 const void* bwd_out_kernel(Prec prec, int tangent, int ng, int* slot) {
-  const bool small = ng <= kWaveLocalGates;
+  const bool small = ng <= kSmallMaxGates;
   *slot = 12 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0) + (small ? 4 : 0);
-  return small ? bwd_out_kernel_g<kWaveLocalGates>(prec, tangent) : bwd_out_kernel_g<kMaxGates>(prec, tangent);
+  return small ? bwd_out_kernel_g<kSmallMaxGates>(prec, tangent) : bwd_out_kernel_g<kMaxGates>(prec, tangent);
 }
 
 int bwd_grid(Prec prec, int tangent, int ng, long long items, int from_output) {
