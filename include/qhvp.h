@@ -80,6 +80,16 @@ const char* qhvp_last_error(void);
 /* Number of gates K of an n-qubit, L-layer open brickwall (Sec. III), or -1 if n < 2 or L < 1. */
 int qhvp_num_gates(int n, int L);
 
+/* The pass plan the library uses for an n-qubit, L-layer brickwall (host only, no device needed).
+ * A pass applies up to 5 gates to tiles of at most 2^10 amplitudes spanned by the low 4 index bits
+ * and a window of consecutive bits; gates of several layers share a pass, in an order that keeps
+ * every gate after the gates of the previous layer on overlapping qubits.  Returns the number of
+ * passes (or a negative status); if gates_per_pass is non-NULL it receives that many counts
+ * (capacity max_passes), and if gate_order is non-NULL it receives the K gate indices in the order
+ * of application (capacity K = qhvp_num_gates(n, L)).  Errors return -QHVP_ERR_INVALID (message in
+ * qhvp_last_error). */
+int qhvp_plan(int n, int L, int max_passes, int* gates_per_pass, int* gate_order);
+
 /* Create / destroy a context bound to HIP device `device`. */
 qhvp_status qhvp_ctx_create(int device, qhvp_ctx** out);
 void qhvp_ctx_destroy(qhvp_ctx* ctx);

@@ -40,6 +40,7 @@ _SIGS = {
     "qhvp_version": (C.c_int, []),
     "qhvp_last_error": (C.c_char_p, []),
     "qhvp_num_gates": (C.c_int, [C.c_int, C.c_int]),
+    "qhvp_plan": (C.c_int, [C.c_int, C.c_int, C.c_int, _ip, _ip]),
     "qhvp_ctx_create": (C.c_int, [C.c_int, C.POINTER(_vp)]),
     "qhvp_ctx_destroy": (None, [_vp]),
     "qhvp_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int]),

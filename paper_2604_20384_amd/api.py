@@ -21,6 +21,20 @@ def num_gates(n: int, L: int) -> int:
     return lib.qhvp_num_gates(n, L)
 
 
+def plan(n: int, L: int):
+    """The library's pass plan: (gates per pass, gate indices in application order)."""
+    K = num_gates(n, L)
+    np_ = lib.qhvp_plan(n, L, 0, None, None)
+    if np_ < 0:
+        check(-np_)
+    per = (C.c_int * np_)()
+    order = (C.c_int * K)()
+    got = lib.qhvp_plan(n, L, np_, per, order)
+    if got < 0:
+        check(-got)
+    return list(per), list(order)
+
+
 def workspace_bytes(n, L, L_ref, n_samples, precision="c128", ckpt_every=1, with_tangent=True) -> int:
     return int(lib.qhvp_workspace_bytes(n, L, L_ref, n_samples, PRECISIONS[precision], ckpt_every,
                                         1 if with_tangent else 0))

@@ -833,6 +833,27 @@ const char* qhvp_last_error(void) { return g_err.c_str(); }
 
 int qhvp_num_gates(int n, int L) { return num_gates(n, L); }
 
+int qhvp_plan(int n, int L, int max_passes, int* gates_per_pass, int* gate_order) {
+  if (n < 2 || n > qhvp::kMaxQubits || L < 1) {
+    fail(QHVP_ERR_INVALID, "n must be in [2, 30] and L >= 1");
+    return -QHVP_ERR_INVALID;
+  }
+  const auto passes = plan_circuit(n, L, nullptr);
+  const int np = (int)passes.size();
+  if (gates_per_pass && max_passes < np) {
+    fail(QHVP_ERR_INVALID, "gates_per_pass holds " + std::to_string(max_passes) + " entries, the plan has " +
+                               std::to_string(np) + " passes");
+    return -QHVP_ERR_INVALID;
+  }
+  int k = 0;
+  for (int q = 0; q < np; ++q) {
+    if (gates_per_pass) gates_per_pass[q] = passes[q].ng;
+    for (int j = 0; j < passes[q].ng; ++j, ++k)
+      if (gate_order) gate_order[k] = passes[q].gidx[j];
+  }
+  return np;
+}
+
 qhvp_status qhvp_ctx_create(int device, qhvp_ctx** out) {
   if (!out) return fail(QHVP_ERR_INVALID, "out is NULL");
   int cnt = 0;

@@ -1,0 +1,55 @@
+"""The pass planner (host logic, no device): passes of several brickwall layers must apply every
+gate exactly once, each after the gates of the previous layer on overlapping qubits, so that the
+planned order computes the same circuit as the layer order."""
+import numpy as np
+import pytest
+
+from oracle import circuit
+from paper_2604_20384_amd.inputs import haar_unitary
+
+
+def _plan(n, L):
+    from paper_2604_20384_amd import api
+    return api.plan(n, L)
+
+
+@pytest.mark.parametrize("n,L", [(2, 1), (2, 5), (3, 4), (5, 3), (6, 4), (9, 7), (10, 4), (12, 5), (16, 12),
+                                 (20, 20), (23, 6), (30, 3)])
+def test_plan_is_a_dependency_respecting_permutation(n, L):
+    per, order = _plan(n, L)
+    pos = circuit.brickwall_positions(n, L)   # gate k -> (layer, q)
+    K = len(pos)
+    assert sorted(order) == list(range(K)) and sum(per) == K
+    assert all(1 <= c <= 5 for c in per)
+    when = {k: i for i, k in enumerate(order)}
+    for k, (l, q) in enumerate(pos):
+        for k2, (l2, q2) in enumerate(pos):
+            if l2 == l - 1 and abs(q2 - q) <= 1:   # previous layer, overlapping qubits
+                assert when[k2] < when[k], (n, L, k, k2)
+
+
+def test_plan_sizes():
+    """Several layers per pass: n=20, L=20 (190 gates) takes 40 passes; one layer per pass would need 60."""
+    per, _ = _plan(20, 20)
+    assert len(per) == 40
+
+
+@pytest.mark.parametrize("n,L", [(7, 6), (10, 5)])
+def test_planned_order_computes_the_same_circuit(n, L):
+    rng = np.random.default_rng(n * 31 + L)
+    pos = circuit.brickwall_positions(n, L)
+    G = haar_unitary(rng, 4, len(pos))
+    psi = rng.standard_normal(2 ** n) + 1j * rng.standard_normal(2 ** n)
+    ref = circuit.apply_circuit(psi[:, None], G, n, L)[:, 0]
+    _, order = _plan(n, L)
+    out = psi.copy()
+    for k in order:
+        out = circuit.apply_gate(out[:, None], G[k], pos[k][1], n)[:, 0]
+    assert np.allclose(out, ref, atol=1e-12)
+
+
+def test_plan_rejects_bad_shapes():
+    from paper_2604_20384_amd import _lib
+    assert _lib.lib.qhvp_plan(1, 3, 0, None, None) < 0
+    assert _lib.lib.qhvp_plan(31, 3, 0, None, None) < 0
+    assert _lib.lib.qhvp_plan(20, 20, 3, (_lib.C.c_int * 3)(), None) < 0
