@@ -7,7 +7,7 @@
 
 namespace qhvp {
 
-// A pass applies up to kMaxGates gates of one brickwall layer to a tile of
+// A pass applies up to kMaxGates gates (in dependency order) to a tile of
 // 2^mb amplitudes (mb <= kMaxTileBits) of one sample.  The tile's "active"
 // bits abit[0..mb) are statevector index bits (ascending); the low kCoalesce
 // bits are always active so that global loads and stores touch contiguous

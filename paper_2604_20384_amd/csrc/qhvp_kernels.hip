@@ -5,9 +5,11 @@
 // Data layout: a state set is N_s contiguous statevectors of 2^n complex
 // amplitudes (sample-major).  A pass loads, for one sample at a time, a tile
 // of 2^mb amplitudes spanned by the pass's active index bits into LDS,
-// applies its gates (all from one layer, so they act on disjoint qubit pairs
-// and commute) one after another with a workgroup barrier between gates, and
-// writes the tile back (or reduces it against phi0).  The low index bits are
+// applies its gates (possibly from several layers, in dependency order) one
+// after another, and writes the tile back (or reduces it against phi0).  When
+// two tile bits are untouched by every gate of the pass, they index the waves
+// and each wave works on its own quarter of the tile with no barrier between
+// gates; otherwise a workgroup barrier separates gates.  The low index bits are
 // always active, so each global access covers contiguous runs of amplitudes.
 //
 // Backward pass: the tile holds the backward states (a, b) at the pass output
