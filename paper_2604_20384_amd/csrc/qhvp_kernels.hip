@@ -377,16 +377,17 @@ struct StepRaw {
   int off[kOffs];
   float2 gb[2], gi[2];
 };
+__device__ __forceinline__ void load_gates(const float2* sGV, int j, int e_fwd, int e_bwd, StepRaw& r) {
+  r.gb[0] = sGV[64 * j + e_bwd];
+  r.gb[1] = sGV[64 * j + 16 + e_bwd];
+  r.gi[0] = sGV[64 * j + 32 + e_fwd];
+  r.gi[1] = sGV[64 * j + 48 + e_fwd];
+}
 __device__ __forceinline__ void load_step(const int* sOff, const float2* sGV, int j, int e_fwd, int e_bwd,
                                           bool with_gates, StepRaw& r) {
 #pragma unroll
   for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
-  if (with_gates) {
-    r.gb[0] = sGV[64 * j + e_bwd];
-    r.gb[1] = sGV[64 * j + 16 + e_bwd];
-    r.gi[0] = sGV[64 * j + 32 + e_fwd];
-    r.gi[1] = sGV[64 * j + 48 + e_fwd];
-  }
+  if (with_gates) load_gates(sGV, j, e_fwd, e_bwd, r);
 }
 
 // Padded LDS indices of the 4 amplitudes of group g (2*b_hi + b_lo order).
@@ -1138,17 +1139,20 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
 
-    // complex64 with at most 4 gates: the step tables are loaded one step ahead (registers permitting)
-    constexpr bool kPipe = kF32 && MAXG <= kSmallMaxGates;
+    // complex64: the step's offsets (and, with at most 4 gates, its gate entries) are loaded one
+    // step ahead, as far as registers permit
+    constexpr bool kPipe = kF32;
+    constexpr bool kPipeGates = kF32 && MAXG <= kSmallMaxGates;
     StepRaw nxt;
-    if (kPipe) load_step(sOff, sGV, ng - 1, e_fwd, e_bwd, true, nxt);
+    if (kPipe) load_step(sOff, sGV, ng - 1, e_fwd, e_bwd, kPipeGates, nxt);
 #pragma unroll
     for (int j = MAXG - 1; j >= 0; --j) {
       if (j < ng) {
         StepRaw cur;
         if (kPipe) {
           cur = nxt;
-          if (j > 0) load_step(sOff, sGV, j - 1, e_fwd, e_bwd, true, nxt);
+          if (j > 0) load_step(sOff, sGV, j - 1, e_fwd, e_bwd, kPipeGates, nxt);
+          if (!kPipeGates) load_gates(sGV, j, e_fwd, e_bwd, cur);
         } else {
           load_step(sOff, sGV, j, e_fwd, e_bwd, kF32, cur);
         }
