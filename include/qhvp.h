@@ -81,7 +81,7 @@ const char* qhvp_last_error(void);
 int qhvp_num_gates(int n, int L);
 
 /* The pass plan the library uses for an n-qubit, L-layer brickwall (host only, no device needed).
- * A pass applies up to 5 gates to tiles of at most 2^10 amplitudes spanned by the low 4 index bits
+ * A pass applies up to 6 gates to tiles of at most 2^10 amplitudes spanned by the low 4 index bits
  * and a window of consecutive bits; gates of several layers share a pass, in an order that keeps
  * every gate after the gates of the previous layer on overlapping qubits.  Returns the number of
  * passes (or a negative status); if gates_per_pass is non-NULL it receives that many counts

@@ -12,7 +12,7 @@ namespace qhvp {
 // bits abit[0..mb) are statevector index bits (ascending); the low kCoalesce
 // bits are always active so that global loads and stores touch contiguous
 // runs.  The remaining (inactive) bits ibit[0..n-mb) enumerate the tiles.
-constexpr int kMaxGates = 5;
+constexpr int kMaxGates = 6;
 constexpr int kSmallMaxGates = 4;   // passes of at most this many gates use a lighter kernel instance
 constexpr int kMaxTileBits = 10;
 constexpr int kMaxQubits = 30;

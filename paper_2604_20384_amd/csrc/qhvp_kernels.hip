@@ -644,13 +644,37 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   }
 }
 
+// complex64 environment accumulation.  A wave's FP32 MFMA accumulator holds one tile's partial sums
+// of one gate slot (64 products per element); right after its step the wave stages it in LDS
+// (stg[(w * MAXG + j) * 256 + 4 * lane + r]), so no accumulator outlives its step.  Between the
+// end of that tile and the next tile's first barrier every thread adds the four waves' values of
+// its own element e = 4 * lane + r, in wave order and in FP64, into one FP64 running sum per gate
+// slot (sAcc[j * 256 + e]): the workgroup keeps 256 doubles per gate.
+template <int MAXG>
+__device__ __forceinline__ void env_put(const Mfma<float>::acc_t& e, float* stg, int j, int tid) {
+  const int wave = tid >> 6, lane = tid & 63;
+  *(qv4f*)(stg + (wave * MAXG + j) * 256 + 4 * lane) = e;
+}
+template <int MAXG>
+__device__ __forceinline__ void env_reduce(const float* stg, double* sAcc, int ng, int tid) {
+#pragma unroll
+  for (int j = 0; j < MAXG; ++j) {
+    if (j < ng) {
+      double v = 0;
+#pragma unroll
+      for (int w = 0; w < kThreads / 64; ++w) v += (double)stg[(w * MAXG + j) * 256 + tid];
+      sAcc[j * 256 + tid] += v;
+    }
+  }
+}
+
 // Per-workgroup environment partials after the tile loop: sum the 4 waves' 16x16 MFMA blocks of
 // each gate slot (FP64, fixed order), then combine the real blocks into the 16 complex entries of
 // E = sum conj(a) psi^T and of D = sum conj(b) psi^T + conj(a) dpsi^T:
 // env_part[wg][j][0..32) = E (re, im interleaved, entry 4x + y), [32..64) = D.
 // sRed: kThreads * 4 doubles of LDS that the tile loop no longer uses.
 template <typename R, int MAXG>
-__device__ __forceinline__ void env_partials(typename Mfma<R>::acc_t (&acc)[MAXG], const double* sAcc, double* sRed,
+__device__ __forceinline__ void env_partials(const typename Mfma<R>::acc_t* acc, const double* sAcc, double* sRed,
                                              double* sM, int ng, int tid, double* env_part) {
   using M = Mfma<R>;
   constexpr bool kF32 = std::is_same<R, float>::value;
@@ -658,16 +682,21 @@ __device__ __forceinline__ void env_partials(typename Mfma<R>::acc_t (&acc)[MAXG
 #pragma unroll
   for (int j = 0; j < MAXG; ++j) {
     if (j < ng) {
+      if constexpr (kF32) {
+        // the workgroup's sum of element e = 4 * lane_e + r is already in sAcc (see env_reduce)
+        const int le = tid >> 2, r = tid & 3;
+        sM[M::out_row(le >> 4, r) * 16 + (le & 15)] = sAcc[j * 256 + tid];
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        sRed[(wave * 64 + lane) * 4 + r] = kF32 ? sAcc[(j * 4 + r) * kThreads + tid] : (double)acc[j][r];
-      __syncthreads();
-      if (wave == 0) {
+        for (int r = 0; r < 4; ++r) sRed[(wave * 64 + lane) * 4 + r] = (double)acc[j][r];
+        __syncthreads();
+        if (wave == 0) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          double v = 0;
-          for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[(wv * 64 + lane) * 4 + r];
-          sM[M::out_row(sub, r) * 16 + comp] = v;
+          for (int r = 0; r < 4; ++r) {
+            double v = 0;
+            for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[(wv * 64 + lane) * 4 + r];
+            sM[M::out_row(sub, r) * 16 + comp] = v;
+          }
         }
       }
       __syncthreads();
@@ -717,7 +746,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sM[16 * 16];
   // complex64: FP64 running sums of the per-tile FP32 MFMA accumulators, one column per thread
-  __shared__ double sAcc[kF32 ? MAXG * 4 * kThreads : 1];
+  __shared__ double sAcc[kF32 ? MAXG * 256 : 1];
+  __shared__ __attribute__((aligned(16))) float sStg[kF32 ? 4 * MAXG * 256 : 1];
   __shared__ float2 sGV[kF32 ? kMaxGates * 32 : 1];
   __shared__ int sOff[kMaxGates * kOffs];
 
@@ -760,14 +790,14 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   // the a / psi arrays (in bounds) and their products are discarded.
   const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSP + cri;  // in units of R
 
-  acc_t acc[MAXG];
+  acc_t acc[kF32 ? 1 : MAXG];   // complex128: FP64 sums over all tiles; complex64 stages per step
 #pragma unroll
   for (int j = 0; j < MAXG; ++j) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[j][r] = 0;
   }
   if constexpr (kF32) {
-    for (int i = tid; i < MAXG * 4 * kThreads; i += kThreads) sAcc[i] = 0;
+    for (int i = tid; i < MAXG * 256; i += kThreads) sAcc[i] = 0;
   }
   // Groups g >= ngroups (only when mb < kMaxTileBits) map to tile indices >= 2^mb: zero them once so
   // that their MFMA operands are zero (the gate applications keep them zero).
@@ -867,6 +897,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       IO::write(abA, st0, st_base, xv, TS, tid);
       if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
     }
+    if constexpr (kF32) {
+      // the previous tile's staged partials (staged before its final barrier; this tile stages after
+      // the next one)
+      if (it > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);
+    }
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
 
@@ -934,7 +969,15 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
         }
         pin16(av);
 #pragma unroll
-        for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bop[j][c], acc[j]);
+        for (int c = 0; c < 16; ++c) {
+          if constexpr (kF32) acc[0] = M::step(av[c], bop[j][c], acc[0]);
+          else acc[j] = M::step(av[c], bop[j][c], acc[j]);
+        }
+        if constexpr (kF32) {
+          env_put<MAXG>(acc[0], sStg, j, tid);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[0][r] = 0;
+        }
         if constexpr (kF32) {
           int tw, ch[4];
           w_offsets(O, uwave, lane, tw, ch);
@@ -959,19 +1002,6 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       }
     }
 
-    // ---- complex64: one tile's FP32 partial sums into the FP64 accumulators (LDS, own column)
-    if constexpr (kF32) {
-#pragma unroll
-      for (int j = 0; j < MAXG; ++j) {
-        if (j < ng) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            sAcc[(j * 4 + r) * kThreads + tid] += (double)acc[j][r];
-            acc[j][r] = 0;
-          }
-        }
-      }
-    }
 
     if (a.store_ab) {
       if constexpr (kDefer) {
@@ -992,6 +1022,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
   }
 
+  if constexpr (kF32) {
+    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);   // staged by the last tile, after its barrier
+  }
   env_partials<R, MAXG>(acc, sAcc, (double*)sY, sM, ng, tid, a.env_part);
 }
 
@@ -1021,7 +1054,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   __shared__ __attribute__((aligned(16))) T sX[NST * TSP];
   __shared__ __attribute__((aligned(16))) T sY[NST * TSP];
   __shared__ double sM[16 * 16];
-  __shared__ double sAcc[kF32 ? MAXG * 4 * kThreads : 1];
+  __shared__ double sAcc[kF32 ? MAXG * 256 : 1];
+  __shared__ __attribute__((aligned(16))) float sStg[kF32 ? 4 * MAXG * 256 : 1];
   __shared__ float2 sGV[kF32 ? kMaxGates * 64 : 1];   // per gate slot: G | V | G^-1 | Y
   __shared__ int sOff[kMaxGates * kOffs];
 
@@ -1068,14 +1102,14 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
   const int lane_scalar_off = 2 * (TANG ? cst : 0) * TSP + cri;  // in units of R
 
-  acc_t acc[MAXG];
+  acc_t acc[kF32 ? 1 : MAXG];   // complex128: FP64 sums over all tiles; complex64 stages per step
 #pragma unroll
   for (int j = 0; j < MAXG; ++j) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc[j][r] = 0;
   }
   if constexpr (kF32) {
-    for (int i = tid; i < MAXG * 4 * kThreads; i += kThreads) sAcc[i] = 0;
+    for (int i = tid; i < MAXG * 256; i += kThreads) sAcc[i] = 0;
   }
   for (int t = TS + tid; t < TSMAX; t += kThreads) {
     sX[LD::at(t)] = cz<T>(); sY[LD::at(t)] = cz<T>();
@@ -1136,6 +1170,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       IO::write(abA, st0, st_base, xv, TS, tid);
       if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
     }
+    if constexpr (kF32) {
+      // the previous tile's staged partials (staged before its final barrier; this tile stages after
+      // the next one)
+      if (it > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);
+    }
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
 
@@ -1182,7 +1221,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
           if (undo_ab) wy.pin();
           if (j > 0) wx.pin();
 #pragma unroll
-          for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bx[c], acc[j]);
+          for (int c = 0; c < 16; ++c) acc[0] = M::step(av[c], bx[c], acc[0]);
           if (undo_ab) {
             wy.mfma(w_operands_xy(cur.gb[0], cur.gb[1], true, lane));
             wy.store(sY, sY + TSP, tw, ch);
@@ -1191,6 +1230,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
             wx.mfma(w_operands_xy(cur.gi[0], cur.gi[1], false, lane));
             wx.store(sX, sX + TSP, tw, ch);
           }
+          env_put<MAXG>(acc[0], sStg, j, tid);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[0][r] = 0;
         } else {
           pin16(av);
           pin16(bx);
@@ -1226,18 +1268,6 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       }
     }
 
-    if constexpr (kF32) {
-#pragma unroll
-      for (int j = 0; j < MAXG; ++j) {
-        if (j < ng) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            sAcc[(j * 4 + r) * kThreads + tid] += (double)acc[j][r];
-            acc[j][r] = 0;
-          }
-        }
-      }
-    }
 
     if (a.store_ab) {
       IO::read(st0, sY, tid);
@@ -1251,6 +1281,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   if (st_base >= 0) {
     IO::write(abA, st0, st_base, xv, TS, tid);
     if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+  }
+  if constexpr (kF32) {
+    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);   // staged by the last tile, after its barrier
   }
   env_partials<R, MAXG>(acc, sAcc, (double*)sY, sM, ng, tid, a.env_part);
 }
