@@ -1181,7 +1181,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     // complex64: the step's offsets (and, with at most 4 gates, its gate entries) are loaded one
     // step ahead, as far as registers permit
     constexpr bool kPipe = kF32;
-    constexpr bool kPipeGates = kF32 && MAXG <= kSmallMaxGates;
+    constexpr bool kPipeGates = kF32;
     StepRaw nxt;
     if (kPipe) load_step(sOff, sGV, ng - 1, e_fwd, e_bwd, kPipeGates, nxt);
 #pragma unroll
