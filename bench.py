@@ -2,9 +2,11 @@
 n=20 qubits, L=20 layers (K=190 gates), N_s=256 Haar product samples, U_ref a Haar brickwall
 of depth 40, complex64 states with FP64 accumulation, on one MI355X.
 
-One step = one from-scratch HVP call (cost + gradient + HVP for one (G, V) over all samples);
-the labels phi_s = U_ref psi_s are computed once per problem (the problem statement takes
-them as input) and reported separately as setup time.  Prints one JSON line.
+One step = one from-scratch HVP call (cost + gradient + HVP for one (G, V) over all samples),
+each at its own Haar G, so that no forward state kept from an earlier call belongs to it; the
+labels phi_s = U_ref psi_s are computed once per problem (the problem statement takes them as
+input) and reported separately as setup time.  A second leg ("fixed_G") times HVPs along several
+directions at one G, where the forward states at G are kept between calls.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -40,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--fixed-g-dirs", type=int, default=8,
+                    help="directions of the fixed-G leg (0: skip it)")
     ap.add_argument("--seed", type=int, default=1)
     return ap.parse_args()
 
@@ -135,6 +139,28 @@ def pick_ckpt(n, L, L_ref, ns, precision):
     return 8
 
 
+def fixed_g_leg(gp, G, M, rng, from_scratch_hvps):
+    """HVPs along M directions at one G (hvp_batch) after a gradient call at G, so every direction
+    reads the kept forward states at G and stores only tangents."""
+    import numpy as np
+    import torch
+
+    from paper_2604_20384_amd.inputs import random_tangent
+    Vfix = np.stack([random_tangent(rng, G) for _ in range(M)])
+    gp.grad(G)
+    gp.set_profiling(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gp.hvp_batch(G, Vfix)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stats = gp.kernel_stats()
+    return {"directions": M, "value": round(M / dt, 4), "unit": "HVP/s", "ms_per_hvp": round(1e3 * dt / M, 3),
+            "kernel_ms_per_hvp": {k: round(v["ms"] / M, 3) for k, v in stats.items()},
+            "alg_bytes_per_hvp": sum(v["bytes"] for v in stats.values()) / M,
+            "vs_from_scratch": round(M / dt / from_scratch_hvps, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -149,11 +175,15 @@ def main():
     import torch
 
     from paper_2604_20384_amd.api import Problem, num_gates
-    from paper_2604_20384_amd.inputs import make_problem
+    from paper_2604_20384_amd.inputs import haar_unitary, make_problem, random_tangent
 
     n, L, ns = args.n, args.L, args.ns
     K = num_gates(n, L)
     prob = make_problem(n, L, ns, seed=args.seed)
+    # a fresh Haar G and tangent V for every call: each timed HVP is from scratch
+    rng = np.random.default_rng(args.seed + 1000)
+    Gs = [prob.G] + [haar_unitary(rng, 4, K) for _ in range(args.warmup + args.steps - 1)]
+    Vs = [prob.V] + [random_tangent(rng, G) for G in Gs[1:]]
     if args.ckpt is None:
         args.ckpt = pick_ckpt(n, L, prob.L_ref, ns, args.precision)
     torch.cuda.synchronize()
@@ -163,13 +193,13 @@ def main():
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
 
-    for _ in range(args.warmup):
-        gp.hvp(prob.G, prob.V)
+    for i in range(args.warmup):
+        gp.hvp(Gs[i], Vs[i])
     gp.set_profiling(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        c, g, h = gp.hvp(prob.G, prob.V)
+    for i in range(args.warmup, args.warmup + args.steps):
+        c, g, h = gp.hvp(Gs[i], Vs[i])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stats = gp.kernel_stats()
@@ -229,6 +259,8 @@ def main():
         "kernel_ms_per_step": {k: round(v["ms"] / args.steps, 3) for k, v in stats.items()},
         "roofline": roof,
     }
+    if args.fixed_g_dirs > 0:
+        out["fixed_G"] = fixed_g_leg(gp, prob.G, args.fixed_g_dirs, rng, hvps)
     gp.close()
     del gp
     torch.cuda.empty_cache()

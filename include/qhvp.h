@@ -144,6 +144,22 @@ qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom,
 qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom,
                      double* cost, double* grad, double* hvp);
 
+/* Fixed-G reuse and several directions (Sec. IV: the truncated-CG inner loop takes many HVPs at
+ * one point; App. G: one HVP per tangent basis vector).  The forward states psi that a gradient or
+ * HVP sweep leaves at the pass boundaries kept in the workspace (every boundary with ckpt_every =
+ * 0, the segment checkpoints otherwise) are tagged with the gates G that produced them.  A later
+ * gradient or HVP call whose G is bitwise the same reads them there and stores only the tangent
+ * states over them; its results are identical to those of a call that rewrites them.  Any gradient
+ * or HVP call at another G retags them; qhvp_cost never touches them.
+ * qhvp_hvp_batch evaluates n_dirs HVPs at one G: V and hvp hold n_dirs*K*16 complex (direction m at
+ * offset m*K*16), processed one tangent sweep pair after another; hvp[m] equals qhvp_hvp(G, V[m])
+ * bit for bit.  cost and grad (the gradient at G) may be NULL.  All directions are validated before
+ * any device work; n_dirs < 1 is QHVP_ERR_INVALID.  The problem needs tangent storage. */
+qhvp_status qhvp_hvp_batch(qhvp_problem* p, const double* G, int n_dirs, const double* V, qhvp_geometry geom,
+                           double* cost, double* grad, double* hvp);
+/* 1 if the kept pass-boundary states belong to G (bitwise), 0 if not, -1 for NULL arguments. */
+int qhvp_states_kept_for(const qhvp_problem* p, const double* G);
+
 /* Two-phase form of qhvp_grad / qhvp_hvp (Alg. 1: forward pass, then backward pass).
  * qhvp_forward runs the forward sweep at G (with the tangent sweep along V if V != NULL; V is
  * projected onto the tangent space first when geom is Riemannian), returns the cost and

@@ -50,6 +50,8 @@ _SIGS = {
     "qhvp_cost": (C.c_int, [_vp, _dp, _dp, _dp]),
     "qhvp_grad": (C.c_int, [_vp, _dp, C.c_int, _dp, _dp]),
     "qhvp_hvp": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp, _dp]),
+    "qhvp_hvp_batch": (C.c_int, [_vp, _dp, C.c_int, _dp, C.c_int, _dp, _dp, _dp]),
+    "qhvp_states_kept_for": (C.c_int, [_vp, _dp]),
     "qhvp_forward": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp]),
     "qhvp_backward": (C.c_int, [_vp, _dp, _dp]),
     "qhvp_grad_ti": (C.c_int, [_vp, _dp, C.c_int, _dp, _dp]),

@@ -166,6 +166,32 @@ class Problem:
                            dptr(_f64(g)), dptr(_f64(h))))
         return c.value, g, h
 
+    def hvp_batch(self, G, Vs, riemannian=False):
+        """HVPs at one G along several directions Vs (M, K, 4, 4) -> (cost, grad, (M, K, 4, 4)).
+
+        Equal bit for bit to M calls of `hvp`; the forward states at G are stored by the first
+        direction (or kept from an earlier gradient / HVP call at the same G) and read by the rest."""
+        self.epoch += 1
+        G = _c128(G, (self.K, 4, 4))
+        Vs = _c128(Vs)
+        if Vs.ndim != 4 or Vs.shape[1:] != (self.K, 4, 4) or Vs.shape[0] < 1:
+            raise ValueError(f"Vs must have shape (M, {self.K}, 4, 4) with M >= 1")
+        M = Vs.shape[0]
+        g = np.empty((self.K, 4, 4), dtype=np.complex128)
+        h = np.empty((M, self.K, 4, 4), dtype=np.complex128)
+        c = C.c_double()
+        check(lib.qhvp_hvp_batch(self.handle, dptr(_f64(G)), M, dptr(_f64(Vs)), int(riemannian), C.byref(c),
+                                 dptr(_f64(g)), dptr(_f64(h))))
+        return c.value, g, h
+
+    def states_kept_for(self, G) -> bool:
+        """Whether the forward states kept at the pass boundaries belong to gates G (bitwise)."""
+        G = _c128(G, (self.K, 4, 4))
+        r = lib.qhvp_states_kept_for(self.handle, dptr(_f64(G)))
+        if r < 0:
+            raise ValueError("closed problem")
+        return bool(r)
+
     def forward(self, G, V=None, riemannian=False):
         """Forward sweep (keeps the checkpoints for one `backward`); returns (cost, fidelity)."""
         self.epoch += 1

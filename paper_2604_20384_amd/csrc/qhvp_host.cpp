@@ -441,6 +441,11 @@ struct qhvp_problem {
   std::vector<cd> bwd_Gi, bwd_V;
   qhvp_geometry fwd_geom = QHVP_EUCLIDEAN;
   std::vector<double> fwd_G, fwd_V;
+  // The forward states psi at the pass boundaries that stay in the workspace between calls (every
+  // boundary when there is one segment, else the segment checkpoints) belong to the gates kept_G
+  // while kept_valid: a later gradient / HVP sweep at bitwise the same G stores only tangents there.
+  int kept_valid = 0;
+  std::vector<double> kept_G;
   hipEvent_t ev0, ev1;
   double last_ms;
   // optional per-launch timing: events bracket every launch of the call; stats accumulate per kind
@@ -521,8 +526,9 @@ void to_device_precision(const qhvp_problem* p, const double* src, size_t n_comp
 
 // Forward sweep of `passes` (gates at device pointer `gates`).  mode: 0 = labels (write result to
 // phi0), 1 = ansatz sweep storing checkpoints for a later backward sweep, 2 = ansatz cost only.
+// keep_psi (mode 1): the kept boundaries already hold psi for these gates; store dpsi only there.
 qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& passes, const void* gates,
-                          const void* dirs, int tangent, int mode) {
+                          const void* dirs, int tangent, int mode, bool keep_psi = false) {
   const int np = (int)passes.size();
   const char* samples = p->small(p->lay.o_samples);
   double* ovpart = (double*)p->small(p->lay.o_ovpart);
@@ -544,6 +550,7 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
     a.samples = samples;
     char* src = nullptr;
     char* dst = nullptr;
+    bool dst_kept = false;   // dst is a boundary that later calls find unchanged
     if (mode == 0) {
       src = q == 0 ? nullptr : p->phi0();
       dst = p->phi0();
@@ -559,6 +566,9 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
       if (q == np - 1) dst = nullptr;
       else if (q + 1 == s1) dst = p->ckpt(j + 1);
       else dst = last_seg ? p->segbuf(q + 1 - s0) : p->work();
+      // checkpoints are only written here; with several segments the backward sweep recomputes
+      // into the in-segment buffers, so those are kept only when there is a single segment
+      dst_kept = dst != nullptr && (q + 1 == s1 || J == 1);
     }
     a.src_psi = src;
     a.src_dpsi = src ? p->second(src) : nullptr;
@@ -569,12 +579,13 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
       a.phi0 = p->phi0();
       a.ov_part = ovpart;
     } else {
-      a.dst_psi = dst;
+      a.dst_psi = (keep_psi && dst_kept) ? nullptr : dst;
       a.dst_dpsi = p->second(dst);
     }
     {
       const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
-      const double bytes = (a.src_psi ? nst * S : 0) + (a.ov_part ? S : 0) + (a.dst_psi ? nst * S : 0);
+      const double bytes = (a.src_psi ? nst * S : 0) + (a.ov_part ? S : 0) + (a.dst_psi ? S : 0) +
+                           (tangent && a.dst_dpsi ? S : 0);
       HIP_TRY(prof_begin(p));
       LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
       HIP_TRY(prof_end(p, QHVP_KERNEL_FORWARD, bytes, pass_flops(p, a.pd, tangent, false)));
@@ -751,6 +762,10 @@ qhvp_status phase_forward(qhvp_problem* p, const double* G, const double* V, int
   HIP_TRY(hipSetDevice(p->ctx->device));
   p->fwd_ready = 0;
   p->last_ms = 0;
+  const size_t gn = (size_t)p->K * 32;
+  const bool keep = mode != 0 && p->kept_valid && p->kept_G.size() == gn &&
+                    std::memcmp(p->kept_G.data(), G, gn * sizeof(double)) == 0;
+  if (mode != 0 && !keep) p->kept_valid = 0;   // this sweep overwrites the kept boundaries
   to_device_precision(p, G, (size_t)p->K * 16, p->h_gates);
   HIP_TRY(hipEventRecord(p->ev0, p->stream));
   HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_gates), p->h_gates, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
@@ -766,7 +781,8 @@ qhvp_status phase_forward(qhvp_problem* p, const double* G, const double* V, int
                              p->stream));
   }
   qhvp_status st = mode == 0 ? forward_sweep(p, p->passes, p->small(p->lay.o_gates), nullptr, 0, 2)
-                             : forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent, 1);
+                             : forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent, 1,
+                                             keep);
   if (st) return st;
   HIP_TRY(hipMemcpyAsync(p->h_tov, p->small(p->lay.o_tov), (size_t)p->Ns * 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   st = finish_call(p, 0, tangent);
@@ -784,6 +800,8 @@ qhvp_status phase_forward(qhvp_problem* p, const double* G, const double* V, int
   if (mode != 0) {
     p->fwd_ready = 1;
     p->fwd_tangent = tangent;
+    if (!keep) p->kept_G.assign(G, G + gn);
+    p->kept_valid = 1;
   }
   return QHVP_OK;
 }
@@ -1027,6 +1045,41 @@ qhvp_status qhvp_backward(qhvp_problem* p, double* grad, double* hvp) {
   if (grad) std::memcpy(grad, g.data(), g.size() * sizeof(double));
   if (hvp) std::memcpy(hvp, h.data(), h.size() * sizeof(double));
   return QHVP_OK;
+}
+
+qhvp_status qhvp_hvp_batch(qhvp_problem* p, const double* G, int n_dirs, const double* V, qhvp_geometry geom,
+                           double* cost, double* grad, double* hvp) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (n_dirs < 1) return fail(QHVP_ERR_INVALID, "n_dirs must be positive");
+  if (!V || !hvp) return fail(QHVP_ERR_INVALID, "V and hvp must not be NULL");
+  if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  qhvp_status st = check_gates(p, G, "G");
+  if (st) return st;
+  const size_t gn = (size_t)p->K * 32;
+  if (!finite_all(V, gn * (size_t)n_dirs)) return fail(QHVP_ERR_INVALID, "V has non-finite entries");
+  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->K, G) > 1e-10)
+    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
+  // the first direction stores psi at the kept boundaries (unless they already belong to G); the
+  // others read it there
+  std::vector<double> out(gn * (size_t)n_dirs), g(gn);
+  double c = 0;
+  for (int m = 0; m < n_dirs; ++m) {
+    st = qhvp_forward(p, G, V + gn * m, geom, &c, nullptr);
+    if (st) return st;
+    st = qhvp_backward(p, m == 0 ? g.data() : nullptr, out.data() + gn * m);
+    if (st) return st;
+  }
+  std::memcpy(hvp, out.data(), out.size() * sizeof(double));
+  if (grad) std::memcpy(grad, g.data(), gn * sizeof(double));
+  if (cost) *cost = c;
+  return QHVP_OK;
+}
+
+int qhvp_states_kept_for(const qhvp_problem* p, const double* G) {
+  if (!p || !G) return -1;
+  const size_t gn = (size_t)p->K * 32;
+  return p->kept_valid && p->kept_G.size() == gn && std::memcmp(p->kept_G.data(), G, gn * sizeof(double)) == 0;
 }
 
 qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom, double* cost, double* grad) {

@@ -49,7 +49,8 @@ struct PassDesc {
 enum Prec { P_C128 = 0, P_C64 = 1 };
 
 // Forward pass: states (psi, dpsi) -> W psi (Eq. fis / Eq. dfis).  src_psi == nullptr means
-// "generate the product state psi^[0] from `samples`, with dpsi = 0".  If ov_part != nullptr the
+// "generate the product state psi^[0] from `samples`, with dpsi = 0".  dst_psi and dst_dpsi are
+// stored independently (null: not stored).  If ov_part != nullptr the
 // result is not stored; instead per-tile partial overlaps with phi0 are written:
 // ov_part[s*tiles + w] = (sum conj(phi0) psi, sum conj(phi0) dpsi) as 4 doubles.
 struct FwdArgs {

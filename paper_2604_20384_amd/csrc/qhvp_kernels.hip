@@ -496,6 +496,9 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   const T* __restrict__ samp = (const T*)a.samples;
   const bool gen = (srcP == nullptr);
   const bool ovl = (a.ov_part != nullptr);
+  // psi and dpsi are stored independently: a tangent sweep may leave psi in a boundary buffer that
+  // already holds it (same gates) and store dpsi only
+  const bool stP = dstP != nullptr, stD = TANG && dstD != nullptr;
   const unsigned imask = (unsigned)pd.imask;
   const bool wl = pd.wave_local != 0;
   const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);   // entry of X, Y behind this lane's operands
@@ -559,8 +562,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       }
     }
     if (st_base >= 0) {
-      IO::write(dstP, st0, st_base, xv, TS, tid);
-      if (TANG) IO::write(dstD, st1, st_base, xv, TS, tid);
+      if (stP) IO::write(dstP, st0, st_base, xv, TS, tid);
+      if (stD) IO::write(dstD, st1, st_base, xv, TS, tid);
     }
     __syncthreads();
     if (!gen && it + 1 < it1) QHVP_FWD_PREFETCH(sn, xn);
@@ -629,9 +632,9 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
         a.ov_part[it * 4 + tid] = v;
       }
     }
-    if (dstP != nullptr) {
-      IO::read(st0, sP, tid);
-      if (TANG) IO::read(st1, sD, tid);
+    if (stP || stD) {
+      if (stP) IO::read(st0, sP, tid);
+      if (stD) IO::read(st1, sD, tid);
       st_base = base;
     }
     __syncthreads();
@@ -639,8 +642,8 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
     x = xn;
   }
   if (st_base >= 0) {
-    IO::write(dstP, st0, st_base, xv, TS, tid);
-    if (TANG) IO::write(dstD, st1, st_base, xv, TS, tid);
+    if (stP) IO::write(dstP, st0, st_base, xv, TS, tid);
+    if (stD) IO::write(dstD, st1, st_base, xv, TS, tid);
   }
 }
 

@@ -26,17 +26,24 @@ def tangent_basis(G: np.ndarray) -> np.ndarray:
     return E
 
 
-def riemannian_hessian(hvp_fn, G: np.ndarray) -> np.ndarray:
-    """Dense (16K x 16K) matrix from `hvp_fn(G, V) -> H_R[V]` (Riemannian HVP) on the basis."""
+def riemannian_hessian(hvp_fn, G: np.ndarray, batch_fn=None, batch: int = 64) -> np.ndarray:
+    """Dense (16K x 16K) matrix from `hvp_fn(G, V) -> H_R[V]` (Riemannian HVP) on the basis, or from
+    `batch_fn(G, Vs) -> H_R[Vs]` on `batch` basis vectors at a time when given."""
     E = tangent_basis(G)
     n = E.shape[0]
     H = np.empty((n, n))
-    for j in range(n):
-        HV = hvp_fn(G, E[j])
-        H[:, j] = np.real(np.einsum("ikab,kab->i", np.conj(E), HV))
+    for j0 in range(0, n, batch if batch_fn is not None else 1):
+        if batch_fn is not None:
+            HV = batch_fn(G, E[j0:j0 + batch])
+        else:
+            HV = hvp_fn(G, E[j0])[None]
+        for i, hv in enumerate(HV):
+            H[:, j0 + i] = np.real(np.einsum("ikab,kab->i", np.conj(E), hv))
     return H
 
 
-def problem_hessian(problem, G: np.ndarray) -> np.ndarray:
-    """Riemannian Hessian of a `api.Problem` at unitary gates G."""
-    return riemannian_hessian(lambda g, v: problem.hvp(g, v, riemannian=True)[2], G)
+def problem_hessian(problem, G: np.ndarray, batch: int = 64) -> np.ndarray:
+    """Riemannian Hessian of a `api.Problem` at unitary gates G; the columns are HVPs at one G, taken
+    `batch` directions per call so that the forward states at G are computed once."""
+    return riemannian_hessian(None, G, batch_fn=lambda g, vs: problem.hvp_batch(g, vs, riemannian=True)[2],
+                              batch=batch)

@@ -87,6 +87,8 @@ def test_errors_are_reported_not_raised_in_c():
     st = lib.qhvp_ctx_create(10 ** 6, ctypes.byref(h))      # no such device (or no GPU at all)
     assert st in (_lib.QHVP_ERR_INVALID, _lib.QHVP_ERR_DEVICE)
     assert lib.qhvp_overlaps(None, None, None) == _lib.QHVP_ERR_INVALID
+    assert lib.qhvp_hvp_batch(None, None, 1, None, 0, None, None, None) == _lib.QHVP_ERR_INVALID
+    assert lib.qhvp_states_kept_for(None, None) == -1
 
 
 def test_product_path_has_no_fallback():
