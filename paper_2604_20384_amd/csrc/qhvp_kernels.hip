@@ -383,6 +383,14 @@ __device__ __forceinline__ void load_gates(const float2* sGV, int j, int e_fwd, 
   r.gi[0] = sGV[64 * j + 32 + e_fwd];
   r.gi[1] = sGV[64 * j + 48 + e_fwd];
 }
+// The forward kernel's step: the gate's offsets and this lane's entries of its G, V (gi[0], gi[1];
+// sGV holds G | V, 32 entries per gate slot).
+__device__ __forceinline__ void load_fwd_step(const int* sOff, const float2* sGV, int j, int e_fwd, StepRaw& r) {
+#pragma unroll
+  for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
+  r.gi[0] = sGV[32 * j + e_fwd];
+  r.gi[1] = sGV[32 * j + 16 + e_fwd];
+}
 __device__ __forceinline__ void load_step(const int* sOff, const float2* sGV, int j, int e_fwd, int e_bwd,
                                           bool with_gates, StepRaw& r) {
 #pragma unroll
@@ -535,6 +543,11 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   // stores too, so stores issued right before that wait would be waited for as well.
   typename IO::V st0[IO::NV], st1[IO::NV];
   long long st_base = -1;
+  StepRaw nxt;
+  if constexpr (kF32) {
+    __syncthreads();   // the staged tables
+    load_fwd_step(sOff, sGV, 0, e_fwd, nxt);
+  }
 
   for (long long it = it0; it < it1; ++it) {
     const long long sbase = (long long)s * dim;
@@ -569,13 +582,18 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
     if (!gen && it + 1 < it1) QHVP_FWD_PREFETCH(sn, xn);
 
     for (int j = 0; j < ng; ++j) {
-      const GateOff O = gate_offsets(sOff, j);
       if constexpr (kF32) {
+        // this step's tables were loaded one step ahead; load the next step's (the next tile's
+        // first after the last gate: the tables do not change between tiles)
+        const StepRaw cur = nxt;
+        load_fwd_step(sOff, sGV, j + 1 < ng ? j + 1 : 0, e_fwd, nxt);
+        const GateOff O = gate_offsets_raw(cur.off);
         int tl, ch[4];
         w_offsets(O, wave, lane, tl, ch);
-        const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_fwd, false, lane);
+        const qv4f A = w_operands_xy(cur.gi[0], cur.gi[1], false, lane);
         apply_w_mfma<TANG>(A, sP, sD, tl, ch);
       } else {
+        const GateOff O = gate_offsets(sOff, j);
         const auto Gk = opaque(G + 16 * pd.gidx[j]);
         const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
         if (tid < ngroups) {
