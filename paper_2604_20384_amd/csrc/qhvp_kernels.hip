@@ -676,17 +676,20 @@ __device__ __forceinline__ void env_put(const Mfma<float>::acc_t& e, float* stg,
   const int wave = tid >> 6, lane = tid & 63;
   *(qv4f*)(stg + (wave * MAXG + j) * 256 + 4 * lane) = e;
 }
+// All MAXG slots are reduced, used or not (an unused slot's sum is never read): without a branch
+// per slot the loads of every slot are in flight together.
 template <int MAXG>
-__device__ __forceinline__ void env_reduce(const float* stg, double* sAcc, int ng, int tid) {
+__device__ __forceinline__ void env_reduce(const float* stg, double* sAcc, int tid) {
+  double v[MAXG], acc[MAXG];
 #pragma unroll
   for (int j = 0; j < MAXG; ++j) {
-    if (j < ng) {
-      double v = 0;
+    v[j] = 0;
 #pragma unroll
-      for (int w = 0; w < kThreads / 64; ++w) v += (double)stg[(w * MAXG + j) * 256 + tid];
-      sAcc[j * 256 + tid] += v;
-    }
+    for (int w = 0; w < kThreads / 64; ++w) v[j] += (double)stg[(w * MAXG + j) * 256 + tid];
+    acc[j] = sAcc[j * 256 + tid];
   }
+#pragma unroll
+  for (int j = 0; j < MAXG; ++j) sAcc[j * 256 + tid] = acc[j] + v[j];
 }
 
 // Per-workgroup environment partials after the tile loop: sum the 4 waves' 16x16 MFMA blocks of
@@ -921,7 +924,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
     if constexpr (kF32) {
       // the previous tile's staged partials (staged before its final barrier; this tile stages after
       // the next one)
-      if (it > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);
+      if (it > it0) env_reduce<MAXG>(sStg, sAcc, tid);
     }
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
@@ -1044,7 +1047,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   }
 
   if constexpr (kF32) {
-    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);   // staged by the last tile, after its barrier
+    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, tid);   // staged by the last tile, after its barrier
   }
   env_partials<R, MAXG>(acc, sAcc, (double*)sY, sM, ng, tid, a.env_part);
 }
@@ -1194,7 +1197,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     if constexpr (kF32) {
       // the previous tile's staged partials (staged before its final barrier; this tile stages after
       // the next one)
-      if (it > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);
+      if (it > it0) env_reduce<MAXG>(sStg, sAcc, tid);
     }
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
@@ -1304,7 +1307,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
   }
   if constexpr (kF32) {
-    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, ng, tid);   // staged by the last tile, after its barrier
+    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, tid);   // staged by the last tile, after its barrier
   }
   env_partials<R, MAXG>(acc, sAcc, (double*)sY, sM, ng, tid, a.env_part);
 }
