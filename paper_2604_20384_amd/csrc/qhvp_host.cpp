@@ -278,8 +278,11 @@ struct Layout {
   size_t off_phi0 = 0, off_slots = 0, off_small = 0, total = 0;
   size_t slot_bytes = 0;
   // small buffers (offsets from off_small)
-  size_t o_samples, o_gates, o_dirs, o_igates, o_uref, o_tov, o_ovpart, o_envpart, o_env;
+  size_t o_samples, o_gates, o_dirs, o_igates, o_uref, o_tov, o_ovpart, o_envpart, o_env, o_sched;
 };
+
+// Tile-schedule counters (one int per launch, zeroed at the start of every sweep)
+constexpr int kSchedSlots = 4096;
 
 bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_every, int tangent,
                  Layout& lay) {
@@ -312,6 +315,7 @@ bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_
   lay.o_ovpart = o;  o = align_up(o + (size_t)Ns * lay.tiles_max * 4 * sizeof(double) * 2);
   lay.o_envpart = o; o = align_up(o + (size_t)lay.n_wg_max * qhvp::kMaxGates * qhvp::kEnvVals * sizeof(double));
   lay.o_env = o;     o = align_up(o + (size_t)K * qhvp::kEnvVals * sizeof(double));
+  lay.o_sched = o;   o = align_up(o + (size_t)kSchedSlots * sizeof(int));
   lay.total = lay.off_small + o;
   return true;
 }
@@ -450,6 +454,7 @@ struct qhvp_problem {
   double last_ms;
   // optional per-launch timing: events bracket every launch of the call; stats accumulate per kind
   int profiling = 0;
+  int sched_used = 0;   // tile-schedule counters handed out since the last reset
   std::vector<hipEvent_t> evpool;
   size_t ev_used = 0;
   struct Pending { int kind; size_t e0; double bytes, flops; };
@@ -509,6 +514,17 @@ hipError_t prof_collect(qhvp_problem* p) {
 // it, not counting the in-tile recomputation): S bytes per state set read or written; per gate
 // and amplitude 32 flop for psi <- G psi, 96 with the tangent; the backward adds the environment
 // products (32 flop, 96 with the tangent).
+// Tile-schedule counters: zeroed at the start of each sweep; every kernel launch takes a fresh one
+// (all in stream order, so a re-zeroing when the slots run out follows the launches that used them).
+hipError_t sched_reset(qhvp_problem* p) {
+  p->sched_used = 0;
+  return hipMemsetAsync(p->small(p->lay.o_sched), 0, (size_t)kSchedSlots * sizeof(int), p->stream);
+}
+int* sched_slot(qhvp_problem* p) {
+  if (p->sched_used == kSchedSlots && sched_reset(p) != hipSuccess) return nullptr;
+  return (int*)p->small(p->lay.o_sched) + p->sched_used++;
+}
+
 double state_bytes_alg(const qhvp_problem* p) { return (double)p->Ns * std::ldexp(1.0, p->n) * (double)p->amp(); }
 double pass_flops(const qhvp_problem* p, const qhvp::PassDesc& pd, int tangent, bool backward) {
   const double per = tangent ? 96.0 : 32.0;
@@ -539,10 +555,12 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
   for (size_t j = 0; j < p->seg.size(); ++j)
     for (int q = p->seg[j].first; q < p->seg[j].second; ++q) seg_of[q] = (int)j;
   const int J = (int)p->seg.size();
+  HIP_TRY(sched_reset(p));
   for (int q = 0; q < np; ++q) {
     qhvp::FwdArgs a;
     std::memset(&a, 0, sizeof(a));
     a.pd = passes[q];
+    a.sched = sched_slot(p);
     a.n_samples = p->Ns;
     a.tangent = tangent;
     a.gates = gates;
@@ -607,6 +625,7 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
   double* envpart = (double*)p->small(p->lay.o_envpart);
   double* env = (double*)p->small(p->lay.o_env);
   char* ab = p->work();
+  HIP_TRY(sched_reset(p));
   for (int j = J - 1; j >= 0; --j) {
     const int s0 = p->seg[j].first, s1 = p->seg[j].second;
     char* start = j == 0 ? nullptr : p->ckpt(j);
@@ -616,6 +635,7 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
         qhvp::FwdArgs a;
         std::memset(&a, 0, sizeof(a));
         a.pd = p->passes[q];
+        a.sched = sched_slot(p);
         a.n_samples = p->Ns;
         a.tangent = tangent;
         a.gates = gates;

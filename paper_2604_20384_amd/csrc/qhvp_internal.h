@@ -64,6 +64,8 @@ struct FwdArgs {
   void* dst_psi; void* dst_dpsi;
   const void* phi0;
   double* ov_part;
+  int* sched;          // tile-schedule counter of this launch (zero before the launch)
+  int chunk;           // tiles per chunk of the schedule (set by launch_fwd)
 };
 
 // Backward pass over the same tile structure: (a, b) at the pass output -> at the pass input

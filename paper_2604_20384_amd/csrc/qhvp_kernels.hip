@@ -474,7 +474,9 @@ __device__ __forceinline__ T product_amp(const T* u, int n, long long x) {
 // Forward pass
 // --------------------------------------------------------------------------------------------
 template <typename R, bool TANG>
-__global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
+// complex64: at least 4 waves per SIMD (registers <= 128), which the latency-bound forward needs
+__global__ void __launch_bounds__(kThreads)
+    __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 4 : 1, 8))) k_fwd(FwdArgs a) {
   using T = typename CT<R>::T;
   using LD = Lds<T>;
   using IO = TileIO<T>;
@@ -485,6 +487,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
   __shared__ double sRed[kThreads / 64][4];
   __shared__ float2 sGV[kF32 ? kMaxGates * 32 : 1];
   __shared__ int sOff[kMaxGates * kOffs];
+  __shared__ int sSch[2];
 
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
@@ -518,14 +521,27 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
 #pragma unroll
   for (int v = 0; v < IO::NV; ++v) xv[v] = (int)deposit(IO::elem(tid, v), pd.abit, mb);
 
-  const long long it0 = items * blockIdx.x / gridDim.x;
-  const long long it1 = items * (blockIdx.x + 1) / gridDim.x;
+  // Dynamic schedule: tiles are handed out in chunks of CH consecutive tiles from the launch's
+  // counter (zeroed by the host), so a workgroup that runs ahead takes more and all finish together
+  // (several workgroups share a CU and the hardware serves the oldest first: with a static split the
+  // younger ones finished last, on a half-empty CU).  Thread 0 requests the next chunk at the start
+  // of a chunk's first tile and publishes it in LDS at that tile's end, hiding the request's
+  // latency; from then on the chunk's last tile can prefetch the next chunk's first tile.
+  // (tile indices fit in 32 bits: the host checks items < 2^31)
+  const int nit = (int)items, CH = a.chunk;
+  const int nch = (nit + CH - 1) / CH;
+  if (tid == 0) sSch[0] = atomicAdd(a.sched, 1);
+  __syncthreads();
+  int c = sSch[0], cn = -1;                   // current chunk; the next one once known
+  int it = c * CH;                            // current tile (item)
+  int cend = c < nch ? min(it + CH, nit) : it;
+  int pend = 0;                               // thread 0: the next chunk, requested at a chunk's start
   // current tile: sample s, offset x = pdep(tile index within the sample, imask)
   int s = 0;
   unsigned x = 0;
-  if (it0 < it1) {
-    s = (int)(it0 / tiles);
-    x = (unsigned)deposit(it0 - (long long)s * tiles, pd.ibit, n - mb);
+  if (c < nch) {
+    s = it / tiles;
+    x = (unsigned)deposit(it - s * tiles, pd.ibit, n - mb);
   }
 
   // the next tile's loads are in flight while the current tile is computed
@@ -538,7 +554,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       if (TANG) pf1[v] = *(const typename IO::V*)(srcD + bn_ + xv[v]);                              \
     }                                                                                               \
   }
-  if (!gen && it0 < it1) QHVP_FWD_PREFETCH(s, x);
+  if (!gen && c < nch) QHVP_FWD_PREFETCH(s, x);
   // The stores of tile t are issued after tile t+1's loads have been waited for: vmcnt counts
   // stores too, so stores issued right before that wait would be waited for as well.
   typename IO::V st0[IO::NV], st1[IO::NV];
@@ -549,11 +565,26 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
     load_fwd_step(sOff, sGV, 0, e_fwd, nxt);
   }
 
-  for (long long it = it0; it < it1; ++it) {
+  while (c < nch) {
+    const bool firstt = (it == c * CH);
+    if (firstt && tid == 0) pend = atomicAdd(a.sched, 1);
     const long long sbase = (long long)s * dim;
     const long long base = sbase + x;
-    const unsigned xn = next_tile(x, imask);
-    const int sn = s + (xn == 0u ? 1 : 0);
+    // the next tile: the next one of this chunk, else the first of the next chunk (known from the
+    // end of this chunk's first tile; unknown during a chunk of one tile)
+    bool hn = false;
+    int sn = 0;
+    unsigned xn = 0;
+    if (it + 1 < cend) {
+      hn = true;
+      xn = next_tile(x, imask);
+      sn = s + (xn == 0u ? 1 : 0);
+    } else if (!firstt && cn < nch) {
+      hn = true;
+      const int itn = cn * CH;
+      sn = itn / tiles;
+      xn = (unsigned)deposit(itn - sn * tiles, pd.ibit, n - mb);
+    }
     if (gen) {
       if (tid < 2 * n) sU[tid] = samp[(long long)s * 2 * n + tid];
       __syncthreads();
@@ -579,7 +610,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       if (stD) IO::write(dstD, st1, st_base, xv, TS, tid);
     }
     __syncthreads();
-    if (!gen && it + 1 < it1) QHVP_FWD_PREFETCH(sn, xn);
+    if (!gen && hn) QHVP_FWD_PREFETCH(sn, xn);
 
     for (int j = 0; j < ng; ++j) {
       if constexpr (kF32) {
@@ -647,7 +678,7 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       if (tid < 4) {
         double v = 0;
         for (int wv = 0; wv < kThreads / 64; ++wv) v += sRed[wv][tid];
-        a.ov_part[it * 4 + tid] = v;
+        a.ov_part[(long long)it * 4 + tid] = v;
       }
     }
     if (stP || stD) {
@@ -655,9 +686,29 @@ __global__ void __launch_bounds__(kThreads) k_fwd(FwdArgs a) {
       if (stD) IO::read(st1, sD, tid);
       st_base = base;
     }
+    if (firstt && tid == 0) sSch[1] = pend;
     __syncthreads();
-    s = sn;
-    x = xn;
+    if (firstt) cn = sSch[1];
+    if (it + 1 < cend) {
+      ++it;
+      s = sn;
+      x = xn;
+    } else {
+      c = cn;
+      cn = -1;
+      it = c * CH;
+      cend = c < nch ? min(it + CH, nit) : it;
+      if (c < nch) {
+        if (hn) {
+          s = sn;
+          x = xn;
+        } else {
+          s = it / tiles;
+          x = (unsigned)deposit(it - s * tiles, pd.ibit, n - mb);
+          if (!gen) QHVP_FWD_PREFETCH(s, x);
+        }
+      }
+    }
   }
   if (st_base >= 0) {
     if (stP) IO::write(dstP, st0, st_base, xv, TS, tid);
@@ -1424,9 +1475,18 @@ int bwd_grid(Prec prec, int tangent, int ng, long long items, int from_output) {
   return pick_grid(items, resident_wgs(k, slot));
 }
 
-int launch_fwd(Prec prec, const FwdArgs& a, void* stream) {
-  const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
-  dim3 grid(fwd_grid(prec, a.tangent, items)), block(kThreads);
+// Tiles per chunk of the dynamic schedule: about 32 chunks per workgroup (a late workgroup's tail is
+// at most one chunk), between 1 and 64 tiles.
+int sched_chunk(long long items, int grid) {
+  long long c = items / ((long long)grid * 32);
+  return (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
+}
+int launch_fwd(Prec prec, const FwdArgs& a0, void* stream) {
+  const long long items = (long long)a0.n_samples << (a0.pd.n - a0.pd.mb);
+  if (a0.sched == nullptr || items >= (1LL << 31)) return (int)hipErrorInvalidValue;
+  dim3 grid(fwd_grid(prec, a0.tangent, items)), block(kThreads);
+  FwdArgs a = a0;
+  a.chunk = sched_chunk(items, (int)grid.x);
   hipStream_t st = (hipStream_t)stream;
   if (prec == P_C64) {
     if (a.tangent) hipLaunchKernelGGL((k_fwd<float, true>), grid, block, 0, st, a);
