@@ -800,6 +800,19 @@ __device__ __forceinline__ void env_partials(const typename Mfma<R>::acc_t* acc,
   }
 }
 
+// Two workgroups share each CU in the backward kernels (registers and LDS allow no more), and the
+// hardware serves the older one first: with an even static split of the tiles the younger one fell
+// behind and finished its share alone, on a half-empty CU.  The grid's two halves (workgroups b and
+// b + grid/2, dispatched one round apart, so one older and one younger per CU) therefore take turns
+// at the higher wave priority, in windows of 2^13 ticks (82 us) of the device's 100 MHz clock, so
+// that both progress at the same average rate.  Which tiles a workgroup computes does not change,
+// so results are unaffected.
+__device__ __forceinline__ void share_cu_turns(unsigned half) {
+  const unsigned rt = (unsigned)__builtin_amdgcn_s_memrealtime();
+  if (((rt >> 13) ^ half) & 1u) __builtin_amdgcn_s_setprio(1);
+  else __builtin_amdgcn_s_setprio(0);
+}
+
 // --------------------------------------------------------------------------------------------
 // Backward pass with environment accumulation
 // --------------------------------------------------------------------------------------------
@@ -912,7 +925,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   typename IO::V st0[IO::NV], st1[IO::NV];
   long long st_base = -1;
 
+  const unsigned half = blockIdx.x >= gridDim.x / 2 ? 1u : 0u;
   for (long long it = it0; it < it1; ++it) {
+    share_cu_turns(half);
     const long long sbase = (long long)s * dim;
     const long long base = sbase + x;
     const unsigned xn = next_tile(x, imask);
@@ -1207,7 +1222,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   typename IO::V st0[IO::NV], st1[IO::NV];
   long long st_base = -1;
 
+  const unsigned half = blockIdx.x >= gridDim.x / 2 ? 1u : 0u;
   for (long long it = it0; it < it1; ++it) {
+    share_cu_turns(half);
     const long long base = (long long)s * dim + x;
     const unsigned xn = next_tile(x, imask);
     const int sn = s + (xn == 0u ? 1 : 0);
