@@ -65,7 +65,7 @@ struct FwdArgs {
   const void* phi0;
   double* ov_part;
   int* sched;          // tile-schedule counter of this launch (zero before the launch)
-  int chunk;           // tiles per chunk of the schedule (set by launch_fwd)
+  int chunk;           // set by launch_fwd: > 0 dynamic chunks of that many tiles; < 0 static ranges of -chunk tiles
 };
 
 // Backward pass over the same tile structure: (a, b) at the pass output -> at the pass input
@@ -87,6 +87,7 @@ struct BwdArgs {
   // launch_bwd_out only: forward states are the pass OUTPUT (src_*), igates = G^-1 | -G^-1 V G^-1
   // per gate (32 complex), fold passes read src_* too (no generated states)
   const void* igates;
+  int turns;           // set by the launchers: 1 when two workgroups share each CU (priority turns)
 };
 
 // Upper bound of the workgroup count of any pass kernel over `items` tiles (sizes per-workgroup

@@ -527,12 +527,17 @@ __global__ void __launch_bounds__(kThreads)
   // younger ones finished last, on a half-empty CU).  Thread 0 requests the next chunk at the start
   // of a chunk's first tile and publishes it in LDS at that tile's end, hiding the request's
   // latency; from then on the chunk's last tile can prefetch the next chunk's first tile.
-  // (tile indices fit in 32 bits: the host checks items < 2^31)
-  const int nit = (int)items, CH = a.chunk;
+  // (tile indices fit in 32 bits: the host checks items < 2^31).  Launches with few tiles per
+  // workgroup use a static split instead (chunk < 0: workgroup b takes range b of -chunk tiles),
+  // where the counter's round trips would not pay for themselves.
+  const bool dyn = a.chunk > 0;
+  const int nit = (int)items, CH = dyn ? a.chunk : -a.chunk;
   const int nch = (nit + CH - 1) / CH;
-  if (tid == 0) sSch[0] = atomicAdd(a.sched, 1);
-  __syncthreads();
-  int c = sSch[0], cn = -1;                   // current chunk; the next one once known
+  if (dyn) {
+    if (tid == 0) sSch[0] = atomicAdd(a.sched, 1);
+    __syncthreads();
+  }
+  int c = dyn ? sSch[0] : (int)blockIdx.x, cn = -1;   // current chunk; the next one once known
   int it = c * CH;                            // current tile (item)
   int cend = c < nch ? min(it + CH, nit) : it;
   int pend = 0;                               // thread 0: the next chunk, requested at a chunk's start
@@ -567,7 +572,7 @@ __global__ void __launch_bounds__(kThreads)
 
   while (c < nch) {
     const bool firstt = (it == c * CH);
-    if (firstt && tid == 0) pend = atomicAdd(a.sched, 1);
+    if (firstt && tid == 0) pend = dyn ? atomicAdd(a.sched, 1) : nch;
     const long long sbase = (long long)s * dim;
     const long long base = sbase + x;
     // the next tile: the next one of this chunk, else the first of the next chunk (known from the
@@ -927,7 +932,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 
   const unsigned half = blockIdx.x >= gridDim.x / 2 ? 1u : 0u;
   for (long long it = it0; it < it1; ++it) {
-    share_cu_turns(half);
+    if (a.turns) share_cu_turns(half);
     const long long sbase = (long long)s * dim;
     const long long base = sbase + x;
     const unsigned xn = next_tile(x, imask);
@@ -1224,7 +1229,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
 
   const unsigned half = blockIdx.x >= gridDim.x / 2 ? 1u : 0u;
   for (long long it = it0; it < it1; ++it) {
-    share_cu_turns(half);
+    if (a.turns) share_cu_turns(half);
     const long long base = (long long)s * dim + x;
     const unsigned xn = next_tile(x, imask);
     const int sn = s + (xn == 0u ? 1 : 0);
@@ -1444,6 +1449,18 @@ int resident_wgs(const void* kern, int slot) {
   return c;
 }
 
+// Compute units of the current device (cached per device).
+int device_cus() {
+  static int cache[16] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
+  if (!cache[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cache[dev] = cus;
+  }
+  return cache[dev];
+}
 int pick_grid(long long items, int resident) {
   const long long g = items < resident ? items : resident;
   return (int)(g < 2048 ? g : 2048);
@@ -1493,17 +1510,20 @@ int bwd_grid(Prec prec, int tangent, int ng, long long items, int from_output) {
 }
 
 // Tiles per chunk of the dynamic schedule: about 32 chunks per workgroup (a late workgroup's tail is
-// at most one chunk), between 1 and 64 tiles.
+// at most one chunk), between 4 and 64 tiles (from the second tile of a chunk on, the next chunk is
+// known and its first tile can be prefetched; a chunk of one tile would load its successor
+// without overlap).
 int sched_chunk(long long items, int grid) {
   long long c = items / ((long long)grid * 32);
-  return (int)(c < 1 ? 1 : (c > 64 ? 64 : c));
+  return (int)(c < 4 ? 4 : (c > 64 ? 64 : c));
 }
 int launch_fwd(Prec prec, const FwdArgs& a0, void* stream) {
   const long long items = (long long)a0.n_samples << (a0.pd.n - a0.pd.mb);
   if (a0.sched == nullptr || items >= (1LL << 31)) return (int)hipErrorInvalidValue;
   dim3 grid(fwd_grid(prec, a0.tangent, items)), block(kThreads);
   FwdArgs a = a0;
-  a.chunk = sched_chunk(items, (int)grid.x);
+  // dynamic chunks when every workgroup has at least 16 tiles on average, else a static split
+  a.chunk = items >= 16LL * grid.x ? sched_chunk(items, (int)grid.x) : -(int)((items + grid.x - 1) / grid.x);
   hipStream_t st = (hipStream_t)stream;
   if (prec == P_C64) {
     if (a.tangent) hipLaunchKernelGGL((k_fwd<float, true>), grid, block, 0, st, a);
@@ -1520,7 +1540,9 @@ int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
   int slot;
   const void* k = bwd_kernel(prec, a.tangent, a.pd.ng, &slot);
   dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
-  void* args[] = {(void*)&a};
+  BwdArgs b = a;
+  b.turns = (int)grid.x > device_cus() ? 1 : 0;   // two workgroups per CU
+  void* args[] = {(void*)&b};
   return (int)hipLaunchKernel(k, grid, block, args, 0, (hipStream_t)stream);
 }
 
@@ -1529,7 +1551,9 @@ int launch_bwd_out(Prec prec, const BwdArgs& a, void* stream) {
   int slot;
   const void* k = bwd_out_kernel(prec, a.tangent, a.pd.ng, &slot);
   dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
-  void* args[] = {(void*)&a};
+  BwdArgs b = a;
+  b.turns = (int)grid.x > device_cus() ? 1 : 0;   // two workgroups per CU
+  void* args[] = {(void*)&b};
   return (int)hipLaunchKernel(k, grid, block, args, 0, (hipStream_t)stream);
 }
 
