@@ -30,6 +30,9 @@
 // give -(N_s/2) conj(grad C) and -(N_s/2) conj(H(C)[V]).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
+#include <cstring>
+
 #include <type_traits>
 
 #include "qhvp_internal.h"
@@ -1523,7 +1526,12 @@ int launch_fwd(Prec prec, const FwdArgs& a0, void* stream) {
   dim3 grid(fwd_grid(prec, a0.tangent, items)), block(kThreads);
   FwdArgs a = a0;
   // dynamic chunks when every workgroup has at least 16 tiles on average, else a static split
-  a.chunk = items >= 16LL * grid.x ? sched_chunk(items, (int)grid.x) : -(int)((items + grid.x - 1) / grid.x);
+  // (QHVP_SCHEDULE=static, read at every launch, forces the static split; the results are the
+  // same either way)
+  const char* sched_env = std::getenv("QHVP_SCHEDULE");
+  const bool force_static = sched_env != nullptr && std::strcmp(sched_env, "static") == 0;
+  const bool dyn = !force_static && items >= 16LL * grid.x;
+  a.chunk = dyn ? sched_chunk(items, (int)grid.x) : -(int)((items + grid.x - 1) / grid.x);
   hipStream_t st = (hipStream_t)stream;
   if (prec == P_C64) {
     if (a.tangent) hipLaunchKernelGGL((k_fwd<float, true>), grid, block, 0, st, a);
