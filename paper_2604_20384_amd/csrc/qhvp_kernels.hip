@@ -210,10 +210,20 @@ template <typename T> struct TileIO {
     else { o.x = r[0]; o.y = r[1]; }
     return o;
   }
-  // element-wise LDS access of one 16-byte vector (complex64 elements need not be 16-byte aligned)
+  // element-wise LDS access of one 16-byte vector (complex64 elements need not be 16-byte aligned).
+  // complex64: 64-bit LDS writes are served 16 lanes at a time over 32 banks of 4 bytes, and the 16
+  // lanes of a group hold 32 consecutive elements, so if every lane wrote its element t first,
+  // elements r and r + 16 would meet on the same banks.  Lanes 8..15 of each group write t + 1
+  // first, which makes both write instructions conflict-free.
   static __device__ __forceinline__ void put(T* lds, int t, int TS, const V& r) {
+    if constexpr (sizeof(T) == 8) {
+      const int sw = (threadIdx.x >> 3) & 1;
+      lds[slot(t + sw, TS)] = part(r, sw);
+      lds[slot(t + 1 - sw, TS)] = part(r, 1 - sw);
+    } else {
 #pragma unroll
-    for (int e = 0; e < EPV; ++e) lds[slot(t + e, TS)] = part(r, e);
+      for (int e = 0; e < EPV; ++e) lds[slot(t + e, TS)] = part(r, e);
+    }
   }
   static __device__ __forceinline__ V get(const T* lds, int t) {
     V r;
