@@ -518,7 +518,7 @@ hipError_t prof_collect(qhvp_problem* p) {
 // (all in stream order, so a re-zeroing when the slots run out follows the launches that used them).
 hipError_t sched_reset(qhvp_problem* p) {
   p->sched_used = 0;
-  return hipMemsetAsync(p->small(p->lay.o_sched), 0, (size_t)kSchedSlots * sizeof(int), p->stream);
+  return (hipError_t)qhvp::launch_zero_ints((int*)p->small(p->lay.o_sched), kSchedSlots, p->stream);
 }
 int* sched_slot(qhvp_problem* p) {
   if (p->sched_used == kSchedSlots && sched_reset(p) != hipSuccess) return nullptr;

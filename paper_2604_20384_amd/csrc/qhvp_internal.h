@@ -103,6 +103,8 @@ int launch_fwd(Prec prec, const FwdArgs& a, void* stream);
 int launch_bwd(Prec prec, const BwdArgs& a, void* stream);
 // Backward pass from the pass-output forward states (see k_bwd_out); same grid as launch_bwd.
 int launch_bwd_out(Prec prec, const BwdArgs& a, void* stream);
+// p[0..n) = 0 (a kernel, not a memset).
+int launch_zero_ints(int* p, int n, void* stream);
 // tov[s] = (T_s, Omega_s) = sum over tiles of ov_part.
 int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream);
 // env[gidx[j]][0..64) = sum over wg of env_part[wg][j][0..64), for j < ng.

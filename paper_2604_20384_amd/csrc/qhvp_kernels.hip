@@ -1575,6 +1575,17 @@ int launch_bwd_out(Prec prec, const BwdArgs& a, void* stream) {
   return (int)hipLaunchKernel(k, grid, block, args, 0, (hipStream_t)stream);
 }
 
+// Zero n ints (the tile-schedule counters) with a kernel rather than a memset node, which stays
+// correct when the caller captures the stream into a graph.
+__global__ void __launch_bounds__(256) k_zero_ints(int* __restrict__ p, int n) {
+  for (int i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
+}
+int launch_zero_ints(int* p, int n, void* stream) {
+  const int blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(k_zero_ints, dim3(blocks < 64 ? blocks : 64), dim3(256), 0, (hipStream_t)stream, p, n);
+  return (int)hipGetLastError();
+}
+
 int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream) {
   hipLaunchKernelGGL(k_reduce_overlaps, dim3(n_samples), dim3(256), 0, (hipStream_t)stream, ov_part, n_samples,
                      tiles, tov);
