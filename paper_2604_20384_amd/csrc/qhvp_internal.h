@@ -92,9 +92,9 @@ struct BwdArgs {
 
 // Upper bound of the workgroup count of any pass kernel over `items` tiles (sizes per-workgroup
 // buffers); fwd_grid / bwd_grid give the count actually launched on the current device (at most
-// the workgroups that are resident at once).
+// the workgroups that are resident at once; 0 for a gate count outside 1..kMaxGates).
 int grid_size(long long items);
-int fwd_grid(Prec prec, int tangent, long long items);
+int fwd_grid(Prec prec, int tangent, int ng, long long items);
 int bwd_grid(Prec prec, int tangent, int ng, long long items, int from_output);
 
 

@@ -30,6 +30,7 @@
 // give -(N_s/2) conj(grad C) and -(N_s/2) conj(H(C)[V]).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 
@@ -308,15 +309,25 @@ __device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int
 // the wave-uniform offset of chain c.  Groups beyond the tile (tiles of fewer than 2^kMaxTileBits
 // amplitudes) hold tile indices >= 2^mb only: they are transformed and written back like the others,
 // which leaves a zeroed tail zero (W 0 = 0) and never touches an index below 2^mb.
+// Byte offsets ad[c] of this lane's element of chain c, shared by every state array of the tile.
+// The lane part is made opaque so that the compiler keeps each array's LDS base as an instruction
+// offset (one add per chain for all arrays) instead of folding it into a base register per array.
+__device__ __forceinline__ void tile_addr(int tl, const int (&ch)[4], int (&ad)[4]) {
+  int tb = 8 * tl;
+  asm volatile("" : "+v"(tb));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) ad[c] = tb + 8 * ch[c];
+}
+
 template <bool TANG>
 struct WTile {
   float2 p[4], d[4];
   Mfma<float>::acc_t r[4];
-  __device__ __forceinline__ void load(const float2* sP, const float2* sD, int tl, const int (&ch)[4]) {
+  __device__ __forceinline__ void load(const float2* sP, const float2* sD, const int (&ad)[4]) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      p[c] = sP[tl + ch[c]];
-      if (TANG) d[c] = sD[tl + ch[c]];
+      p[c] = *(const float2*)((const char*)sP + ad[c]);
+      if (TANG) d[c] = *(const float2*)((const char*)sD + ad[c]);
     }
   }
   __device__ __forceinline__ void pin() {
@@ -340,22 +351,24 @@ struct WTile {
       }
     }
   }
-  __device__ __forceinline__ void store(float2* sP, float2* sD, int tl, const int (&ch)[4]) const {
+  __device__ __forceinline__ void store(float2* sP, float2* sD, const int (&ad)[4]) const {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      sP[tl + ch[c]] = make_float2(r[c][0], r[c][1]);
-      if (TANG) sD[tl + ch[c]] = make_float2(r[c][2], r[c][3]);
+      *(float2*)((char*)sP + ad[c]) = make_float2(r[c][0], r[c][1]);
+      if (TANG) *(float2*)((char*)sD + ad[c]) = make_float2(r[c][2], r[c][3]);
     }
   }
 };
 
 template <bool TANG>
 __device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* sD, int tl, const int (&ch)[4]) {
+  int ad[4];
+  tile_addr(tl, ch, ad);
   WTile<TANG> w;
-  w.load(sP, sD, tl, ch);
+  w.load(sP, sD, ad);
   w.pin();
   w.mfma(A);
-  w.store(sP, sD, tl, ch);
+  w.store(sP, sD, ad);
 }
 
 __device__ __forceinline__ int bitsel(int v, int b, int off) { return ((v >> b) & 1) ? off : 0; }
@@ -450,6 +463,22 @@ __device__ __forceinline__ void w_offsets(const GateOff& o, int wave, int lane, 
   ch[3] = wv + go[4] + go[5];
 }
 
+// The same, with the per-lane selects reading raw (the offsets as loaded from LDS into vector
+// registers, equal in every lane) instead of their scalar copies: a select between a scalar and 0
+// under a lane mask would first copy the scalar into a vector register.
+__device__ __forceinline__ void w_offsets_lane(const GateOff& o, const int (&raw)[kOffs], int wave, int lane, int& tl,
+                                               int (&ch)[4]) {
+  const int* go = o.go;
+  const int col = lane & 15, g = lane >> 4;
+  tl = bitsel(col, 0, raw[0]) + bitsel(col, 1, raw[1]) + bitsel(col, 2, raw[2]) + bitsel(col, 3, raw[3]) +
+       bitsel(g, 0, raw[8]) + bitsel(g, 1, raw[9]);
+  const int wv = bitsel(wave, 0, go[6]) + bitsel(wave, 1, go[7]);
+  ch[0] = wv;
+  ch[1] = wv + go[4];
+  ch[2] = wv + go[5];
+  ch[3] = wv + go[4] + go[5];
+}
+
 // Stage the G (and V) entries of the pass's gates in LDS: sGV[32 j + e] = G_(gidx j)[e],
 // sGV[32 j + 16 + e] = V_(gidx j)[e] (0 without tangent).  Visible after the next barrier.
 template <bool TANG>
@@ -486,7 +515,9 @@ __device__ __forceinline__ T product_amp(const T* u, int n, long long x) {
 // --------------------------------------------------------------------------------------------
 // Forward pass
 // --------------------------------------------------------------------------------------------
-template <typename R, bool TANG>
+// NG > 0: an instance for passes of exactly NG gates (complex64), whose gate steps are unrolled
+// into straight-line code; NG = 0: any gate count (complex128).
+template <typename R, bool TANG, int NG>
 // complex64: at least 4 waves per SIMD (registers <= 128), which the latency-bound forward needs
 __global__ void __launch_bounds__(kThreads)
     __attribute__((amdgpu_waves_per_eu(std::is_same<R, float>::value ? 4 : 1, 8))) k_fwd(FwdArgs a) {
@@ -526,6 +557,8 @@ __global__ void __launch_bounds__(kThreads)
   const unsigned imask = (unsigned)pd.imask;
   const bool wl = pd.wave_local != 0;
   const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);   // entry of X, Y behind this lane's operands
+  static_assert(NG >= 0 && NG <= kMaxGates && (NG > 0) == kF32, "complex64 instances have a fixed gate count");
+  if (NG > 0 && ng != NG) return;   // the launcher picks the instance by the pass's gate count
 
   if constexpr (kF32) stage_gates<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
   stage_offsets(pd, sOff, tid);
@@ -630,15 +663,15 @@ __global__ void __launch_bounds__(kThreads)
     __syncthreads();
     if (!gen && hn) QHVP_FWD_PREFETCH(sn, xn);
 
-    for (int j = 0; j < ng; ++j) {
+    auto gate_step = [&](int j) {
       if constexpr (kF32) {
         // this step's tables were loaded one step ahead; load the next step's (the next tile's
         // first after the last gate: the tables do not change between tiles)
         const StepRaw cur = nxt;
-        load_fwd_step(sOff, sGV, j + 1 < ng ? j + 1 : 0, e_fwd, nxt);
+        load_fwd_step(sOff, sGV, j + 1 < NG ? j + 1 : 0, e_fwd, nxt);
         const GateOff O = gate_offsets_raw(cur.off);
         int tl, ch[4];
-        w_offsets(O, wave, lane, tl, ch);
+        w_offsets_lane(O, cur.off, wave, lane, tl, ch);
         const qv4f A = w_operands_xy(cur.gi[0], cur.gi[1], false, lane);
         apply_w_mfma<TANG>(A, sP, sD, tl, ch);
       } else {
@@ -658,6 +691,12 @@ __global__ void __launch_bounds__(kThreads)
       }
       if (wl && j + 1 < ng) wave_sync();
       else __syncthreads();
+    };
+    if constexpr (NG > 0) {
+#pragma unroll
+      for (int j = 0; j < NG; ++j) gate_step(j);
+    } else {
+      for (int j = 0; j < ng; ++j) gate_step(j);
     }
 
     if (ovl) {
@@ -1188,6 +1227,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   const bool wl = pd.wave_local != 0;
   const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);
   const int e_bwd = 4 * (lane >> 4) + ((lane >> 2) & 3);
+  // complex64 instances are compiled for exactly MAXG gates (the launcher picks the instance by the
+  // pass's gate count), so that the gate steps are straight-line code
+  if (kF32 && ng != MAXG) return;
 
   if constexpr (kF32) {
     for (int j = 0; j < ng; ++j) {
@@ -1296,7 +1338,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     if (kPipe) load_step(sOff, sGV, ng - 1, e_fwd, e_bwd, kPipeGates, nxt);
 #pragma unroll
     for (int j = MAXG - 1; j >= 0; --j) {
-      if (j < ng) {
+      if (kF32 || j < ng) {
         StepRaw cur;
         if (kPipe) {
           cur = nxt;
@@ -1308,24 +1350,30 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         const GateOff O = gate_offsets_raw(cur.off);
         const int* go = O.go;
         const int* ao = O.ao;
-        const int tl = bitsel(sub, 0, go[0]) + bitsel(sub, 1, go[1]) + bitsel(cidx, 0, ao[0]) +
-                       bitsel(cidx, 1, ao[1]) + bitsel(uwave, 0, go[6]) + bitsel(uwave, 1, go[7]);
-        const R* ys = (const R*)sY + lane_scalar_off + 2 * tl;
-        const R* xs = (const R*)sX + lane_scalar_off + 2 * tl;
+        // per-lane selects on the loaded offsets (cur.off), wave-uniform parts scalar
+        const int tl = bitsel(sub, 0, cur.off[0]) + bitsel(sub, 1, cur.off[1]) + bitsel(cidx, 0, cur.off[8]) +
+                       bitsel(cidx, 1, cur.off[9]) + bitsel(uwave, 0, go[6]) + bitsel(uwave, 1, go[7]);
+        (void)ao;
+        // one byte index for both state arrays, opaque so that their LDS bases stay instruction
+        // offsets: one add per operand address
+        int eb = (int)sizeof(R) * (lane_scalar_off + 2 * tl);
+        asm volatile("" : "+v"(eb));
         const bool undo_ab = j > 0 || a.store_ab;   // (a, b) at the pass input are needed
         R av[16], bx[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
           const int uo = ((c & 1) ? go[2] : 0) + ((c & 2) ? go[3] : 0) + ((c & 4) ? go[4] : 0) + ((c & 8) ? go[5] : 0);
-          av[c] = ys[2 * uo];
-          bx[c] = xs[2 * uo];
+          const int ib = eb + 2 * (int)sizeof(R) * uo;
+          av[c] = *(const R*)((const char*)sY + ib);
+          bx[c] = *(const R*)((const char*)sX + ib);
         }
         if constexpr (kF32) {
-          int tw, ch[4];
-          w_offsets(O, uwave, lane, tw, ch);
+          int tw, ch[4], ad[4];
+          w_offsets_lane(O, cur.off, uwave, lane, tw, ch);
+          tile_addr(tw, ch, ad);
           WTile<TANG> wy, wx;
-          if (undo_ab) wy.load(sY, sY + TSP, tw, ch);
-          if (j > 0) wx.load(sX, sX + TSP, tw, ch);
+          if (undo_ab) wy.load(sY, sY + TSP, ad);
+          if (j > 0) wx.load(sX, sX + TSP, ad);
           pin16(av);
           pin16(bx);
           if (undo_ab) wy.pin();
@@ -1334,11 +1382,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
           for (int c = 0; c < 16; ++c) acc[0] = M::step(av[c], bx[c], acc[0]);
           if (undo_ab) {
             wy.mfma(w_operands_xy(cur.gb[0], cur.gb[1], true, lane));
-            wy.store(sY, sY + TSP, tw, ch);
+            wy.store(sY, sY + TSP, ad);
           }
           if (j > 0) {
             wx.mfma(w_operands_xy(cur.gi[0], cur.gi[1], false, lane));
-            wx.store(sX, sX + TSP, tw, ch);
+            wx.store(sX, sX + TSP, ad);
           }
           env_put<MAXG>(acc[0], sStg, j, tid);
 #pragma unroll
@@ -1444,45 +1492,68 @@ __global__ void __launch_bounds__(1024) k_reduce_env(const double* __restrict__ 
 int grid_size(long long items) { return (int)(items < 2048 ? items : 2048); }
 
 namespace {
+// Occupancy cache slots: k_fwd complex64 0..11 (2 (ng - 1) + tangent), complex128 12..13; k_bwd
+// 14..21; k_bwd_out complex128 22..25, complex64 26..37 (26 + 2 (ng - 1) + tangent).
+constexpr int kKernelSlots = 48;
 // Workgroups of `kern` that fit on the current device at once (all CUs), cached per device.  The
 // persistent kernels split their tiles evenly over the grid, so a grid of exactly this many
 // workgroups runs in one round instead of leaving a partial second round.
+// Host threads may launch concurrently: the caches are relaxed atomics (every thread computes the
+// same value, so a lost race only repeats the query).
 int resident_wgs(const void* kern, int slot) {
-  static int cache[16][32] = {};
+  static std::atomic<int> cache[16][kKernelSlots] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 2048;
-  int& c = cache[dev][slot];
-  if (c == 0) {
+  std::atomic<int>& c = cache[dev][slot];
+  int v = c.load(std::memory_order_relaxed);
+  if (v == 0) {
     int per_cu = 0, cus = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || per_cu < 1 || cus < 1)
       return 2048;
-    c = per_cu * cus;
+    v = per_cu * cus;
+    c.store(v, std::memory_order_relaxed);
   }
-  return c;
+  return v;
 }
 
 // Compute units of the current device (cached per device).
 int device_cus() {
-  static int cache[16] = {0};
+  static std::atomic<int> cache[16] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16) return 0;
-  if (!cache[dev]) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    cache[dev] = cus;
+  int v = cache[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    cache[dev].store(v, std::memory_order_relaxed);
   }
-  return cache[dev];
+  return v;
 }
 int pick_grid(long long items, int resident) {
   const long long g = items < resident ? items : resident;
   return (int)(g < 2048 ? g : 2048);
 }
 
-const void* fwd_kernel(Prec prec, int tangent, int* slot) {
-  *slot = (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0);
-  if (prec == P_C64) return tangent ? (const void*)k_fwd<float, true> : (const void*)k_fwd<float, false>;
-  return tangent ? (const void*)k_fwd<double, true> : (const void*)k_fwd<double, false>;
+template <int NG>
+const void* fwd_kernel_c64(int tangent) {
+  return tangent ? (const void*)k_fwd<float, true, NG> : (const void*)k_fwd<float, false, NG>;
+}
+// The instance for a pass of ng gates (complex64: one per gate count), or null for an invalid count.
+const void* fwd_kernel(Prec prec, int tangent, int ng, int* slot) {
+  if (ng < 1 || ng > kMaxGates) return nullptr;
+  if (prec == P_C64) {
+    *slot = 2 * (ng - 1) + (tangent ? 1 : 0);
+    switch (ng) {
+      case 1: return fwd_kernel_c64<1>(tangent);
+      case 2: return fwd_kernel_c64<2>(tangent);
+      case 3: return fwd_kernel_c64<3>(tangent);
+      case 4: return fwd_kernel_c64<4>(tangent);
+      case 5: return fwd_kernel_c64<5>(tangent);
+      default: return fwd_kernel_c64<6>(tangent);
+    }
+  }
+  *slot = 12 + (tangent ? 1 : 0);
+  return tangent ? (const void*)k_fwd<double, true, 0> : (const void*)k_fwd<double, false, 0>;
 }
 
 template <int MAXG>
@@ -1492,34 +1563,52 @@ const void* bwd_kernel_g(Prec prec, int tangent) {
 }
 
 const void* bwd_kernel(Prec prec, int tangent, int ng, int* slot) {
+  if (ng < 1 || ng > kMaxGates) return nullptr;
   const bool small = ng <= kSmallMaxGates;
-  *slot = 4 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0) + (small ? 4 : 0);
+  *slot = 14 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0) + (small ? 4 : 0);
   return small ? bwd_kernel_g<kSmallMaxGates>(prec, tangent) : bwd_kernel_g<kMaxGates>(prec, tangent);
 }
 }  // namespace
 
-int fwd_grid(Prec prec, int tangent, long long items) {
-  int slot;
-  const void* k = fwd_kernel(prec, tangent, &slot);
-  return pick_grid(items, resident_wgs(k, slot));
+int fwd_grid(Prec prec, int tangent, int ng, long long items) {
+  int slot = 0;
+  const void* k = fwd_kernel(prec, tangent, ng, &slot);
+  return k ? pick_grid(items, resident_wgs(k, slot)) : 0;
 }
 
 template <int MAXG>
-const void* bwd_out_kernel_g(Prec prec, int tangent) {
-  if (prec == P_C64) return tangent ? (const void*)k_bwd_out<float, true, MAXG> : (const void*)k_bwd_out<float, false, MAXG>;
+const void* bwd_out_kernel_c128(int tangent) {
   return tangent ? (const void*)k_bwd_out<double, true, MAXG> : (const void*)k_bwd_out<double, false, MAXG>;
 }
 
+template <int NG>
+const void* bwd_out_kernel_c64(int tangent) {
+  return tangent ? (const void*)k_bwd_out<float, true, NG> : (const void*)k_bwd_out<float, false, NG>;
+}
+// complex64: one instance per gate count (straight-line gate steps); complex128: passes of at most
+// kSmallMaxGates gates use the lighter instance.  Null for an invalid count.
 const void* bwd_out_kernel(Prec prec, int tangent, int ng, int* slot) {
+  if (ng < 1 || ng > kMaxGates) return nullptr;
+  if (prec == P_C64) {
+    *slot = 26 + 2 * (ng - 1) + (tangent ? 1 : 0);
+    switch (ng) {
+      case 1: return bwd_out_kernel_c64<1>(tangent);
+      case 2: return bwd_out_kernel_c64<2>(tangent);
+      case 3: return bwd_out_kernel_c64<3>(tangent);
+      case 4: return bwd_out_kernel_c64<4>(tangent);
+      case 5: return bwd_out_kernel_c64<5>(tangent);
+      default: return bwd_out_kernel_c64<6>(tangent);
+    }
+  }
   const bool small = ng <= kSmallMaxGates;
-  *slot = 12 + (prec == P_C64 ? 0 : 2) + (tangent ? 1 : 0) + (small ? 4 : 0);
-  return small ? bwd_out_kernel_g<kSmallMaxGates>(prec, tangent) : bwd_out_kernel_g<kMaxGates>(prec, tangent);
+  *slot = 22 + (tangent ? 1 : 0) + (small ? 2 : 0);
+  return small ? bwd_out_kernel_c128<kSmallMaxGates>(tangent) : bwd_out_kernel_c128<kMaxGates>(tangent);
 }
 
 int bwd_grid(Prec prec, int tangent, int ng, long long items, int from_output) {
-  int slot;
+  int slot = 0;
   const void* k = from_output ? bwd_out_kernel(prec, tangent, ng, &slot) : bwd_kernel(prec, tangent, ng, &slot);
-  return pick_grid(items, resident_wgs(k, slot));
+  return k ? pick_grid(items, resident_wgs(k, slot)) : 0;
 }
 
 // Tiles per chunk of the dynamic schedule: about 32 chunks per workgroup (a late workgroup's tail is
@@ -1532,8 +1621,10 @@ int sched_chunk(long long items, int grid) {
 }
 int launch_fwd(Prec prec, const FwdArgs& a0, void* stream) {
   const long long items = (long long)a0.n_samples << (a0.pd.n - a0.pd.mb);
-  if (a0.sched == nullptr || items >= (1LL << 31)) return (int)hipErrorInvalidValue;
-  dim3 grid(fwd_grid(prec, a0.tangent, items)), block(kThreads);
+  int slot = 0;
+  const void* k = fwd_kernel(prec, a0.tangent, a0.pd.ng, &slot);
+  if (k == nullptr || a0.sched == nullptr || items >= (1LL << 31)) return (int)hipErrorInvalidValue;
+  dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
   FwdArgs a = a0;
   // dynamic chunks when every workgroup has at least 16 tiles on average, else a static split
   // (QHVP_SCHEDULE=static, read at every launch, forces the static split; the results are the
@@ -1542,21 +1633,15 @@ int launch_fwd(Prec prec, const FwdArgs& a0, void* stream) {
   const bool force_static = sched_env != nullptr && std::strcmp(sched_env, "static") == 0;
   const bool dyn = !force_static && items >= 16LL * grid.x;
   a.chunk = dyn ? sched_chunk(items, (int)grid.x) : -(int)((items + grid.x - 1) / grid.x);
-  hipStream_t st = (hipStream_t)stream;
-  if (prec == P_C64) {
-    if (a.tangent) hipLaunchKernelGGL((k_fwd<float, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_fwd<float, false>), grid, block, 0, st, a);
-  } else {
-    if (a.tangent) hipLaunchKernelGGL((k_fwd<double, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_fwd<double, false>), grid, block, 0, st, a);
-  }
-  return (int)hipGetLastError();
+  void* args[] = {(void*)&a};
+  return (int)hipLaunchKernel(k, grid, block, args, 0, (hipStream_t)stream);
 }
 
 int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
   const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
-  int slot;
+  int slot = 0;
   const void* k = bwd_kernel(prec, a.tangent, a.pd.ng, &slot);
+  if (k == nullptr) return (int)hipErrorInvalidValue;
   dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
   BwdArgs b = a;
   b.turns = (int)grid.x > device_cus() ? 1 : 0;   // two workgroups per CU
@@ -1566,8 +1651,9 @@ int launch_bwd(Prec prec, const BwdArgs& a, void* stream) {
 
 int launch_bwd_out(Prec prec, const BwdArgs& a, void* stream) {
   const long long items = (long long)a.n_samples << (a.pd.n - a.pd.mb);
-  int slot;
+  int slot = 0;
   const void* k = bwd_out_kernel(prec, a.tangent, a.pd.ng, &slot);
+  if (k == nullptr) return (int)hipErrorInvalidValue;
   dim3 grid(pick_grid(items, resident_wgs(k, slot))), block(kThreads);
   BwdArgs b = a;
   b.turns = (int)grid.x > device_cus() ? 1 : 0;   // two workgroups per CU
