@@ -9,6 +9,12 @@ from __future__ import annotations
 import ctypes as C
 import os
 
+# PyTorch-ROCm ships its own HIP and HSA runtimes under the same sonames as the system ROCm ones
+# that libqhvp.so links.  Loading torch first makes the library bind to torch's runtime, so the
+# process holds one HIP runtime and device memory is shared freely; loaded the other way round the
+# process would hold two, and whichever initialised second would find no device.
+import torch  # noqa: F401  (load order only)
+
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("QHVP_LIB", os.path.join(_HERE, "libqhvp.so"))
 
