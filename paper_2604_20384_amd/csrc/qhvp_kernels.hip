@@ -1330,32 +1330,93 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
 
-    // complex64: the step's offsets (and, with at most 4 gates, its gate entries) are loaded one
-    // step ahead, as far as registers permit
-    constexpr bool kPipe = kF32;
-    constexpr bool kPipeGates = kF32;
-    StepRaw nxt;
-    if (kPipe) load_step(sOff, sGV, ng - 1, e_fwd, e_bwd, kPipeGates, nxt);
+    if constexpr (kF32) {
+      // The gate steps, software-pipelined inside each wave.  Region A of gate j applies the W
+      // products to (a, b) and (psi, dpsi), whose operands were read earlier, and stores them in
+      // place; after the step barrier, region B issues the reads of gate j-1's W operands (the states
+      // just stored), runs gate j's environment chain on operands read before region A (its 16 MFMAs
+      // cover those reads), stages the chain's sum, and issues the reads of gate j-1's environment
+      // operands (covered by the 32 MFMAs of gate j-1's region A).  Every step still reads the
+      // states its predecessor stored, and the arithmetic and its order are those of the plain
+      // sequence: only the issue order changes.  Offsets and gate entries are loaded two steps ahead.
+      StepRaw rw[2];
+      load_step(sOff, sGV, MAXG - 1, e_fwd, e_bwd, true, rw[(MAXG - 1) & 1]);
+      if (MAXG > 1) load_step(sOff, sGV, MAXG > 1 ? MAXG - 2 : 0, e_fwd, e_bwd, true, rw[(MAXG - 2) & 1]);
+      R av[16], bx[16];
+      WTile<TANG> wy, wx;
+      int ad[4];
+      // environment operands of a gate: one byte index for both state arrays, opaque so that their
+      // LDS bases stay instruction offsets (one add per operand address); per-lane selects on the
+      // loaded offsets, wave-uniform parts scalar
+      auto env_reads = [&](const StepRaw& st, const GateOff& O) {
+        const int tl = bitsel(sub, 0, st.off[0]) + bitsel(sub, 1, st.off[1]) + bitsel(cidx, 0, st.off[8]) +
+                       bitsel(cidx, 1, st.off[9]) + bitsel(uwave, 0, O.go[6]) + bitsel(uwave, 1, O.go[7]);
+        int eb = (int)sizeof(R) * (lane_scalar_off + 2 * tl);
+        asm volatile("" : "+v"(eb));
+#pragma unroll
+        for (int c = 0; c < 16; ++c) {
+          const int uo = ((c & 1) ? O.go[2] : 0) + ((c & 2) ? O.go[3] : 0) + ((c & 4) ? O.go[4] : 0) +
+                         ((c & 8) ? O.go[5] : 0);
+          const int ib = eb + 2 * (int)sizeof(R) * uo;
+          av[c] = *(const R*)((const char*)sY + ib);
+          bx[c] = *(const R*)((const char*)sX + ib);
+        }
+      };
+      // W operands of a gate (the tile addresses ad are kept for the stores)
+      auto w_reads = [&](const StepRaw& st, const GateOff& O, bool ab, bool xs) {
+        int tw, ch[4];
+        w_offsets_lane(O, st.off, uwave, lane, tw, ch);
+        tile_addr(tw, ch, ad);
+        if (ab) wy.load(sY, sY + TSP, ad);
+        if (xs) wx.load(sX, sX + TSP, ad);
+      };
+      {
+        const GateOff O = gate_offsets_raw(rw[(MAXG - 1) & 1].off);
+        env_reads(rw[(MAXG - 1) & 1], O);
+        w_reads(rw[(MAXG - 1) & 1], O, MAXG > 1 || a.store_ab, MAXG > 1);
+      }
+#pragma unroll
+      for (int j = MAXG - 1; j >= 0; --j) {
+        const StepRaw& cur = rw[j & 1];
+        const bool undo_ab = j > 0 || a.store_ab;   // (a, b) at the pass input are needed
+        // region A
+        if (undo_ab) wy.pin();
+        if (j > 0) wx.pin();
+        if (undo_ab) {
+          wy.mfma(w_operands_xy(cur.gb[0], cur.gb[1], true, lane));
+          wy.store(sY, sY + TSP, ad);
+        }
+        if (j > 0) {
+          wx.mfma(w_operands_xy(cur.gi[0], cur.gi[1], false, lane));
+          wx.store(sX, sX + TSP, ad);
+        }
+        if (wl && j > 0) wave_sync();
+        else __syncthreads();
+        // region B
+        const GateOff On = gate_offsets_raw(rw[(j + 1) & 1].off);   // gate j-1's (unused for j = 0)
+        if (j > 0) w_reads(rw[(j + 1) & 1], On, j > 1 || a.store_ab, j > 1);
+        pin16(av);
+        pin16(bx);
+#pragma unroll
+        for (int c = 0; c < 16; ++c) acc[0] = M::step(av[c], bx[c], acc[0]);
+        env_put<MAXG>(acc[0], sStg, j, tid);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[0][r] = 0;
+        if (j > 0) {
+          env_reads(rw[(j + 1) & 1], On);
+          if (j > 1) load_step(sOff, sGV, j > 1 ? j - 2 : 0, e_fwd, e_bwd, true, rw[j & 1]);   // gate j's are done
+        }
+      }
+    } else {
 #pragma unroll
     for (int j = MAXG - 1; j >= 0; --j) {
-      if (kF32 || j < ng) {
+      if (j < ng) {
         StepRaw cur;
-        if (kPipe) {
-          cur = nxt;
-          if (j > 0) load_step(sOff, sGV, j - 1, e_fwd, e_bwd, kPipeGates, nxt);
-          if (!kPipeGates) load_gates(sGV, j, e_fwd, e_bwd, cur);
-        } else {
-          load_step(sOff, sGV, j, e_fwd, e_bwd, kF32, cur);
-        }
+        load_step(sOff, sGV, j, e_fwd, e_bwd, false, cur);
         const GateOff O = gate_offsets_raw(cur.off);
         const int* go = O.go;
-        const int* ao = O.ao;
-        // per-lane selects on the loaded offsets (cur.off), wave-uniform parts scalar
         const int tl = bitsel(sub, 0, cur.off[0]) + bitsel(sub, 1, cur.off[1]) + bitsel(cidx, 0, cur.off[8]) +
                        bitsel(cidx, 1, cur.off[9]) + bitsel(uwave, 0, go[6]) + bitsel(uwave, 1, go[7]);
-        (void)ao;
-        // one byte index for both state arrays, opaque so that their LDS bases stay instruction
-        // offsets: one add per operand address
         int eb = (int)sizeof(R) * (lane_scalar_off + 2 * tl);
         asm volatile("" : "+v"(eb));
         const bool undo_ab = j > 0 || a.store_ab;   // (a, b) at the pass input are needed
@@ -1367,65 +1428,39 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
           av[c] = *(const R*)((const char*)sY + ib);
           bx[c] = *(const R*)((const char*)sX + ib);
         }
-        if constexpr (kF32) {
-          int tw, ch[4], ad[4];
-          w_offsets_lane(O, cur.off, uwave, lane, tw, ch);
-          tile_addr(tw, ch, ad);
-          WTile<TANG> wy, wx;
-          if (undo_ab) wy.load(sY, sY + TSP, ad);
-          if (j > 0) wx.load(sX, sX + TSP, ad);
-          pin16(av);
-          pin16(bx);
-          if (undo_ab) wy.pin();
-          if (j > 0) wx.pin();
+        pin16(av);
+        pin16(bx);
 #pragma unroll
-          for (int c = 0; c < 16; ++c) acc[0] = M::step(av[c], bx[c], acc[0]);
+        for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bx[c], acc[j]);
+        const auto Gk = opaque(G + 16 * pd.gidx[j]);
+        const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
+        const auto GIk = opaque(GI + 32 * pd.gidx[j]);
+        const auto YIk = opaque(GI + 32 * pd.gidx[j] + 16);
+        if (tid < ngroups) {
+          int ix[4];
+          group_index(O, tid, ix);
           if (undo_ab) {
-            wy.mfma(w_operands_xy(cur.gb[0], cur.gb[1], true, lane));
-            wy.store(sY, sY + TSP, ad);
+            T pa[4], pb[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSP + ix[i]]; }
+            apply_wdag<T, TANG>(Gk, Vk, pa, pb);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
           }
           if (j > 0) {
-            wx.mfma(w_operands_xy(cur.gi[0], cur.gi[1], false, lane));
-            wx.store(sX, sX + TSP, ad);
-          }
-          env_put<MAXG>(acc[0], sStg, j, tid);
+            T p[4], d[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[0][r] = 0;
-        } else {
-          pin16(av);
-          pin16(bx);
+            for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
+            apply_w<T, TANG>(GIk, YIk, p, d);
 #pragma unroll
-          for (int c = 0; c < 16; ++c) acc[j] = M::step(av[c], bx[c], acc[j]);
-          const auto Gk = opaque(G + 16 * pd.gidx[j]);
-          const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
-          const auto GIk = opaque(GI + 32 * pd.gidx[j]);
-          const auto YIk = opaque(GI + 32 * pd.gidx[j] + 16);
-          if (tid < ngroups) {
-            int ix[4];
-            group_index(O, tid, ix);
-            if (undo_ab) {
-              T pa[4], pb[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) { pa[i] = sY[ix[i]]; if (TANG) pb[i] = sY[TSP + ix[i]]; }
-              apply_wdag<T, TANG>(Gk, Vk, pa, pb);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
-            }
-            if (j > 0) {
-              T p[4], d[4];
-#pragma unroll
-              for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
-              apply_w<T, TANG>(GIk, YIk, p, d);
-#pragma unroll
-              for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSP + ix[i]] = d[i]; }
-            }
+            for (int i = 0; i < 4; ++i) { sX[ix[i]] = p[i]; if (TANG) sX[TSP + ix[i]] = d[i]; }
           }
         }
         if (wl && j > 0) wave_sync();
         else __syncthreads();
       }
     }
-
+    }
 
     if (a.store_ab) {
       IO::read(st0, sY, tid);
