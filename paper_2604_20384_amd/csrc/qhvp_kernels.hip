@@ -395,33 +395,62 @@ __device__ __forceinline__ void stage_offsets(const PassDesc& pd, int* sOff, int
 struct GateOff {
   int go[8], ao[2];
 };
-// What one backward step of k_bwd_out reads from the per-pass LDS tables, loaded one step ahead
-// so that the step does not start with a chain of LDS round trips: the gate's offsets (made
-// scalar with readfirstlane when used) and, for complex64, this lane's entries of G, V (W^dag
-// operands) and of G^-1, Y (inverse operands).
+// complex64 W operand tables.  Lane l's four A operands of a gate (w_operands_xy) are
+// (A0, A1) = T_odd(u) and (A2, A3) = low ? 0 : T_odd(x), with T_0(v) = (Re v, -Im v),
+// T_1(v) = (Im v, Re v), u = low ? x : y and odd, low = lane bit 0 set, lane bit 1 clear.  The
+// table of one W holds T_0(x), T_1(x), T_0(y), T_1(y) for the 16 entries (kOpTab float2); with a
+// zero entry in the pass's table block, each lane loads its operand pairs directly, from offsets
+// that do not change (OpLane), instead of selecting them per gate.
+constexpr int kOpTab = 64;
+struct OpLane {
+  int o01, o23;   // float2 offsets of (A0, A1) and (A2, A3) within a W table (o23: the zero entry)
+  __device__ __forceinline__ OpLane(int lane, int e, int zero) {
+    const int odd = lane & 1, low = (lane & 2) == 0;
+    o01 = ((low ? 0 : 2) + odd) * 16 + e;
+    o23 = low ? zero : odd * 16 + e;
+  }
+};
+// Table entry t (0 .. kOpTab) of a W with entries x = X[e], y = Y[e] (t = 16 q + e).
+__device__ __forceinline__ float2 op_entry(float2 x, float2 y, int t) {
+  const int q = t >> 4;
+  const float2 v = q < 2 ? x : y;
+  return (q & 1) ? make_float2(v.y, v.x) : make_float2(v.x, -v.y);
+}
+
+// What one backward step of k_bwd_out reads from the per-pass LDS tables, loaded ahead so that the
+// step does not start with a chain of LDS round trips: the gate's offsets (made scalar with
+// readfirstlane when used) and, for complex64, this lane's operand pairs of W^dag (ay) and of the
+// inverse (ax) (the forward kernel: of W, in ax).
 struct StepRaw {
   int off[kOffs];
-  float2 gb[2], gi[2];
+  float2 ay[2], ax[2];
 };
-__device__ __forceinline__ void load_gates(const float2* sGV, int j, int e_fwd, int e_bwd, StepRaw& r) {
-  r.gb[0] = sGV[64 * j + e_bwd];
-  r.gb[1] = sGV[64 * j + 16 + e_bwd];
-  r.gi[0] = sGV[64 * j + 32 + e_fwd];
-  r.gi[1] = sGV[64 * j + 48 + e_fwd];
+// k_bwd_out's table block per gate slot: W^dag table | inverse table | zero entry.
+constexpr int kBwdOpSlot = 2 * kOpTab + 2;
+__device__ __forceinline__ void load_gates(const float2* sGV, int j, const OpLane& ly, const OpLane& lx, StepRaw& r) {
+  r.ay[0] = sGV[kBwdOpSlot * j + ly.o01];
+  r.ay[1] = sGV[kBwdOpSlot * j + ly.o23];
+  r.ax[0] = sGV[kBwdOpSlot * j + kOpTab + lx.o01];   // lx: offsets within the inverse table
+  r.ax[1] = sGV[kBwdOpSlot * j + kOpTab + lx.o23];
 }
-// The forward kernel's step: the gate's offsets and this lane's entries of its G, V (gi[0], gi[1];
-// sGV holds G | V, 32 entries per gate slot).
-__device__ __forceinline__ void load_fwd_step(const int* sOff, const float2* sGV, int j, int e_fwd, StepRaw& r) {
+// k_fwd's table block per gate slot: W table | zero entry.
+constexpr int kFwdOpSlot = kOpTab + 2;
+__device__ __forceinline__ void load_fwd_step(const int* sOff, const float2* sGV, int j, const OpLane& lx, StepRaw& r) {
 #pragma unroll
   for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
-  r.gi[0] = sGV[32 * j + e_fwd];
-  r.gi[1] = sGV[32 * j + 16 + e_fwd];
+  r.ax[0] = sGV[kFwdOpSlot * j + lx.o01];
+  r.ax[1] = sGV[kFwdOpSlot * j + lx.o23];
 }
-__device__ __forceinline__ void load_step(const int* sOff, const float2* sGV, int j, int e_fwd, int e_bwd,
-                                          bool with_gates, StepRaw& r) {
+__device__ __forceinline__ void load_step(const int* sOff, const float2* sGV, int j, const OpLane& ly,
+                                          const OpLane& lx, bool with_gates, StepRaw& r) {
 #pragma unroll
   for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
-  if (with_gates) load_gates(sGV, j, e_fwd, e_bwd, r);
+  if (with_gates) load_gates(sGV, j, ly, lx, r);
+}
+__device__ __forceinline__ qv4f op_quad(const float2 (&a)[2]) {
+  qv4f A;
+  A[0] = a[0].x; A[1] = a[0].y; A[2] = a[1].x; A[3] = a[1].y;
+  return A;
 }
 
 // Padded LDS indices of the 4 amplitudes of group g (2*b_hi + b_lo order).
@@ -490,6 +519,24 @@ __device__ __forceinline__ void stage_gates(const PassDesc& pd, const float2* G,
   }
 }
 
+// The forward kernel's operand tables (complex64): per gate slot j, the table of W = [[G, 0], [V, G]]
+// (V = 0 without tangent) and a zero entry.  Visible after the next barrier.
+template <bool TANG>
+__device__ __forceinline__ void stage_fwd_op_tables(const PassDesc& pd, const float2* G, const float2* V, float2* sGV,
+                                                    int tid) {
+  for (int j = 0; j < pd.ng; ++j) {
+    const int k = pd.gidx[j];
+    if (tid < kOpTab) {
+      const int e = tid & 15;
+      const float2 x = G[16 * k + e];
+      const float2 y = TANG ? V[16 * k + e] : make_float2(0.f, 0.f);
+      sGV[kFwdOpSlot * j + tid] = op_entry(x, y, tid);
+    } else if (tid < kFwdOpSlot) {
+      sGV[kFwdOpSlot * j + tid] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
 // Scatter the low `cnt` bits of v to the statevector bit positions pos[0..cnt).
 __device__ __forceinline__ long long deposit(long long v, const int* pos, int cnt) {
   long long x = 0;
@@ -529,7 +576,7 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ __attribute__((aligned(16))) T sD[TANG ? LD::TSP : 1];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sRed[kThreads / 64][4];
-  __shared__ float2 sGV[kF32 ? kMaxGates * 32 : 1];
+  __shared__ float2 sGV[kF32 ? kMaxGates * kFwdOpSlot : 1];
   __shared__ int sOff[kMaxGates * kOffs];
   __shared__ int sSch[2];
 
@@ -557,10 +604,11 @@ __global__ void __launch_bounds__(kThreads)
   const unsigned imask = (unsigned)pd.imask;
   const bool wl = pd.wave_local != 0;
   const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);   // entry of X, Y behind this lane's operands
+  const OpLane lx(lane, e_fwd, kOpTab);
   static_assert(NG >= 0 && NG <= kMaxGates && (NG > 0) == kF32, "complex64 instances have a fixed gate count");
   if (NG > 0 && ng != NG) return;   // the launcher picks the instance by the pass's gate count
 
-  if constexpr (kF32) stage_gates<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
+  if constexpr (kF32) stage_fwd_op_tables<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
   stage_offsets(pd, sOff, tid);
 
   int xv[IO::NV];
@@ -613,7 +661,7 @@ __global__ void __launch_bounds__(kThreads)
   StepRaw nxt;
   if constexpr (kF32) {
     __syncthreads();   // the staged tables
-    load_fwd_step(sOff, sGV, 0, e_fwd, nxt);
+    load_fwd_step(sOff, sGV, 0, lx, nxt);
   }
 
   while (c < nch) {
@@ -668,11 +716,11 @@ __global__ void __launch_bounds__(kThreads)
         // this step's tables were loaded one step ahead; load the next step's (the next tile's
         // first after the last gate: the tables do not change between tiles)
         const StepRaw cur = nxt;
-        load_fwd_step(sOff, sGV, j + 1 < NG ? j + 1 : 0, e_fwd, nxt);
+        load_fwd_step(sOff, sGV, j + 1 < NG ? j + 1 : 0, lx, nxt);
         const GateOff O = gate_offsets_raw(cur.off);
         int tl, ch[4];
         w_offsets_lane(O, cur.off, wave, lane, tl, ch);
-        const qv4f A = w_operands_xy(cur.gi[0], cur.gi[1], false, lane);
+        const qv4f A = op_quad(cur.ax);
         apply_w_mfma<TANG>(A, sP, sD, tl, ch);
       } else {
         const GateOff O = gate_offsets(sOff, j);
@@ -1203,7 +1251,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   __shared__ double sM[16 * 16];
   __shared__ double sAcc[kF32 ? MAXG * 256 : 1];
   __shared__ __attribute__((aligned(16))) float sStg[kF32 ? 4 * MAXG * 256 : 1];
-  __shared__ float2 sGV[kF32 ? kMaxGates * 64 : 1];   // per gate slot: G | V | G^-1 | Y
+  __shared__ float2 sGV[kF32 ? kMaxGates * kBwdOpSlot : 1];   // per gate slot: W^dag and inverse operand tables
   __shared__ int sOff[kMaxGates * kOffs];
 
   const PassDesc& pd = a.pd;
@@ -1227,19 +1275,33 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   const bool wl = pd.wave_local != 0;
   const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);
   const int e_bwd = 4 * (lane >> 4) + ((lane >> 2) & 3);
+  // zero entry: 2 kOpTab from the slot start, i.e. kOpTab from the inverse table's start
+  const OpLane ly(lane, e_bwd, 2 * kOpTab), lx(lane, e_fwd, kOpTab);
   // complex64 instances are compiled for exactly MAXG gates (the launcher picks the instance by the
   // pass's gate count), so that the gate steps are straight-line code
   if (kF32 && ng != MAXG) return;
 
   if constexpr (kF32) {
+    // operand tables: W^dag = [[G^dag, 0], [V^dag, G^dag]] (its entries enter conjugated, as in
+    // w_operands_xy with conj_) and the inverse [[G^-1, 0], [Y, G^-1]], then a zero entry
     for (int j = 0; j < ng; ++j) {
       const int k = pd.gidx[j];
-      float2 v = make_float2(0.f, 0.f);
-      if (tid < 16) v = ((const float2*)G)[16 * k + tid];
-      else if (tid < 32) { if (TANG) v = ((const float2*)V)[16 * k + tid - 16]; }
-      else if (tid < 48) v = ((const float2*)GI)[32 * k + tid - 32];
-      else if (tid < 64) { if (TANG) v = ((const float2*)GI)[32 * k + tid - 32]; }
-      if (tid < 64) sGV[64 * j + tid] = v;
+      if (tid < 2 * kOpTab) {
+        const int t = tid & (kOpTab - 1), e = t & 15;
+        float2 x, y = make_float2(0.f, 0.f);
+        if (tid < kOpTab) {
+          x = ((const float2*)G)[16 * k + e];
+          if (TANG) y = ((const float2*)V)[16 * k + e];
+          x.y = -x.y;
+          y.y = -y.y;
+        } else {
+          x = ((const float2*)GI)[32 * k + e];
+          if (TANG) y = ((const float2*)GI)[32 * k + 16 + e];
+        }
+        sGV[kBwdOpSlot * j + tid] = op_entry(x, y, t);
+      } else if (tid < kBwdOpSlot) {
+        sGV[kBwdOpSlot * j + tid] = make_float2(0.f, 0.f);
+      }
     }
   }
   stage_offsets(pd, sOff, tid);
@@ -1340,8 +1402,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       // states its predecessor stored, and the arithmetic and its order are those of the plain
       // sequence: only the issue order changes.  Offsets and gate entries are loaded two steps ahead.
       StepRaw rw[2];
-      load_step(sOff, sGV, MAXG - 1, e_fwd, e_bwd, true, rw[(MAXG - 1) & 1]);
-      if (MAXG > 1) load_step(sOff, sGV, MAXG > 1 ? MAXG - 2 : 0, e_fwd, e_bwd, true, rw[(MAXG - 2) & 1]);
+      load_step(sOff, sGV, MAXG - 1, ly, lx, true, rw[(MAXG - 1) & 1]);
+      if (MAXG > 1) load_step(sOff, sGV, MAXG > 1 ? MAXG - 2 : 0, ly, lx, true, rw[(MAXG - 2) & 1]);
       R av[16], bx[16];
       WTile<TANG> wy, wx;
       int ad[4];
@@ -1383,18 +1445,21 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         if (undo_ab) wy.pin();
         if (j > 0) wx.pin();
         if (undo_ab) {
-          wy.mfma(w_operands_xy(cur.gb[0], cur.gb[1], true, lane));
+          wy.mfma(op_quad(cur.ay));
           wy.store(sY, sY + TSP, ad);
         }
         if (j > 0) {
-          wx.mfma(w_operands_xy(cur.gi[0], cur.gi[1], false, lane));
+          wx.mfma(op_quad(cur.ax));
           wx.store(sX, sX + TSP, ad);
         }
         if (wl && j > 0) wave_sync();
         else __syncthreads();
         // region B
-        const GateOff On = gate_offsets_raw(rw[(j + 1) & 1].off);   // gate j-1's (unused for j = 0)
-        if (j > 0) w_reads(rw[(j + 1) & 1], On, j > 1 || a.store_ab, j > 1);
+        GateOff On{};   // gate j-1's offsets
+        if (j > 0) {
+          On = gate_offsets_raw(rw[(j + 1) & 1].off);
+          w_reads(rw[(j + 1) & 1], On, j > 1 || a.store_ab, j > 1);
+        }
         pin16(av);
         pin16(bx);
 #pragma unroll
@@ -1404,7 +1469,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         for (int r = 0; r < 4; ++r) acc[0][r] = 0;
         if (j > 0) {
           env_reads(rw[(j + 1) & 1], On);
-          if (j > 1) load_step(sOff, sGV, j > 1 ? j - 2 : 0, e_fwd, e_bwd, true, rw[j & 1]);   // gate j's are done
+          if (j > 1) load_step(sOff, sGV, j > 1 ? j - 2 : 0, ly, lx, true, rw[j & 1]);   // gate j's are done
         }
       }
     } else {
@@ -1412,7 +1477,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     for (int j = MAXG - 1; j >= 0; --j) {
       if (j < ng) {
         StepRaw cur;
-        load_step(sOff, sGV, j, e_fwd, e_bwd, false, cur);
+        load_step(sOff, sGV, j, ly, lx, false, cur);
         const GateOff O = gate_offsets_raw(cur.off);
         const int* go = O.go;
         const int tl = bitsel(sub, 0, cur.off[0]) + bitsel(sub, 1, cur.off[1]) + bitsel(cidx, 0, cur.off[8]) +
