@@ -424,6 +424,7 @@ __device__ __forceinline__ float2 op_entry(float2 x, float2 y, int t) {
 struct StepRaw {
   int off[kOffs];
   float2 ay[2], ax[2];
+  int lanep;      // complex64: this lane's packed offsets of the gate (lane_offsets)
 };
 // k_bwd_out's table block per gate slot: W^dag table | inverse table | zero entry.
 constexpr int kBwdOpSlot = 2 * kOpTab + 2;
@@ -435,11 +436,13 @@ __device__ __forceinline__ void load_gates(const float2* sGV, int j, const OpLan
 }
 // k_fwd's table block per gate slot: W table | zero entry.
 constexpr int kFwdOpSlot = kOpTab + 2;
-__device__ __forceinline__ void load_fwd_step(const int* sOff, const float2* sGV, int j, const OpLane& lx, StepRaw& r) {
+__device__ __forceinline__ void load_fwd_step(const int* sOff, const float2* sGV, const int* sLane, int j, int lane,
+                                              const OpLane& lx, StepRaw& r) {
 #pragma unroll
   for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
   r.ax[0] = sGV[kFwdOpSlot * j + lx.o01];
   r.ax[1] = sGV[kFwdOpSlot * j + lx.o23];
+  r.lanep = sLane[64 * j + lane];
 }
 __device__ __forceinline__ void load_step(const int* sOff, const float2* sGV, int j, const OpLane& ly,
                                           const OpLane& lx, bool with_gates, StepRaw& r) {
@@ -506,6 +509,40 @@ __device__ __forceinline__ void w_offsets_lane(const GateOff& o, const int (&raw
   ch[1] = wv + go[4];
   ch[2] = wv + go[5];
   ch[3] = wv + go[4] + go[5];
+}
+
+// complex64 per-lane offsets of a pass, computed once per launch (they depend on the gate slot and
+// the lane only): sLane[64 j + l] packs, for lane l and gate slot j, the byte index of the lane's
+// environment operand (low 16 bits; elements of R, second state array included) and 8x the
+// element index of its W-tile element (high 16 bits), both without the wave-uniform parts.
+// Bit-select arithmetic as in w_offsets_lane and the environment operand layout of k_bwd_out.
+__device__ __forceinline__ int lane_offsets(const PassDesc& pd, int j, int l, int tsp, bool tang) {
+  const int* go = pd.goff[j];
+  const int* ao = pd.aoff[j];
+  const int comp = l & 15, sub = l >> 4;
+  const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
+  const int tl = bitsel(sub, 0, go[0]) + bitsel(sub, 1, go[1]) + bitsel(cidx, 0, ao[0]) + bitsel(cidx, 1, ao[1]);
+  const int eb = 4 * (2 * (tang ? cst : 0) * tsp + cri + 2 * tl);
+  const int col = l & 15, g = l >> 4;
+  const int tw = bitsel(col, 0, go[0]) + bitsel(col, 1, go[1]) + bitsel(col, 2, go[2]) + bitsel(col, 3, go[3]) +
+                 bitsel(g, 0, ao[0]) + bitsel(g, 1, ao[1]);
+  return eb | ((8 * tw) << 16);
+}
+// Wave-uniform chain offsets of the W tile (group bits 4, 5 and the wave's bits 6, 7).
+__device__ __forceinline__ void w_chains(const GateOff& o, int wave, int (&ch)[4]) {
+  const int* go = o.go;
+  const int wv = bitsel(wave, 0, go[6]) + bitsel(wave, 1, go[7]);
+  ch[0] = wv;
+  ch[1] = wv + go[4];
+  ch[2] = wv + go[5];
+  ch[3] = wv + go[4] + go[5];
+}
+// Tile byte offsets ad[c] from the lane's packed offsets (high half: 8x its element index).
+__device__ __forceinline__ void tile_addr_packed(int lanep, const int (&ch)[4], int (&ad)[4]) {
+  int tb = (int)((unsigned)lanep >> 16);
+  asm volatile("" : "+v"(tb));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) ad[c] = tb + 8 * ch[c];
 }
 
 // Stage the G (and V) entries of the pass's gates in LDS: sGV[32 j + e] = G_(gidx j)[e],
@@ -577,6 +614,7 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sRed[kThreads / 64][4];
   __shared__ float2 sGV[kF32 ? kMaxGates * kFwdOpSlot : 1];
+  __shared__ int sLane[kF32 ? kMaxGates * 64 : 1];
   __shared__ int sOff[kMaxGates * kOffs];
   __shared__ int sSch[2];
 
@@ -608,7 +646,10 @@ __global__ void __launch_bounds__(kThreads)
   static_assert(NG >= 0 && NG <= kMaxGates && (NG > 0) == kF32, "complex64 instances have a fixed gate count");
   if (NG > 0 && ng != NG) return;   // the launcher picks the instance by the pass's gate count
 
-  if constexpr (kF32) stage_fwd_op_tables<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
+  if constexpr (kF32) {
+    stage_fwd_op_tables<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
+    for (int i = tid; i < ng * 64; i += kThreads) sLane[i] = lane_offsets(pd, i >> 6, i & 63, LD::TSP, TANG);
+  }
   stage_offsets(pd, sOff, tid);
 
   int xv[IO::NV];
@@ -661,7 +702,7 @@ __global__ void __launch_bounds__(kThreads)
   StepRaw nxt;
   if constexpr (kF32) {
     __syncthreads();   // the staged tables
-    load_fwd_step(sOff, sGV, 0, lx, nxt);
+    load_fwd_step(sOff, sGV, sLane, 0, lane, lx, nxt);
   }
 
   while (c < nch) {
@@ -716,12 +757,16 @@ __global__ void __launch_bounds__(kThreads)
         // this step's tables were loaded one step ahead; load the next step's (the next tile's
         // first after the last gate: the tables do not change between tiles)
         const StepRaw cur = nxt;
-        load_fwd_step(sOff, sGV, j + 1 < NG ? j + 1 : 0, lx, nxt);
+        load_fwd_step(sOff, sGV, sLane, j + 1 < NG ? j + 1 : 0, lane, lx, nxt);
         const GateOff O = gate_offsets_raw(cur.off);
-        int tl, ch[4];
-        w_offsets_lane(O, cur.off, wave, lane, tl, ch);
-        const qv4f A = op_quad(cur.ax);
-        apply_w_mfma<TANG>(A, sP, sD, tl, ch);
+        int ch[4], ad[4];
+        w_chains(O, wave, ch);
+        tile_addr_packed(cur.lanep, ch, ad);
+        WTile<TANG> w;
+        w.load(sP, sD, ad);
+        w.pin();
+        w.mfma(op_quad(cur.ax));
+        w.store(sP, sD, ad);
       } else {
         const GateOff O = gate_offsets(sOff, j);
         const auto Gk = opaque(G + 16 * pd.gidx[j]);
@@ -1248,8 +1293,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   // sX: forward states (psi | dpsi) at the current gate's output, sY: backward states (a | b)
   __shared__ __attribute__((aligned(16))) T sX[NST * TSP];
   __shared__ __attribute__((aligned(16))) T sY[NST * TSP];
-  __shared__ double sM[16 * 16];
   __shared__ double sAcc[kF32 ? MAXG * 256 : 1];
+  __shared__ int sLane[kF32 ? MAXG * 64 : 1];
   __shared__ __attribute__((aligned(16))) float sStg[kF32 ? 4 * MAXG * 256 : 1];
   __shared__ float2 sGV[kF32 ? kMaxGates * kBwdOpSlot : 1];   // per gate slot: W^dag and inverse operand tables
   __shared__ int sOff[kMaxGates * kOffs];
@@ -1303,6 +1348,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         sGV[kBwdOpSlot * j + tid] = make_float2(0.f, 0.f);
       }
     }
+    for (int i = tid; i < ng * 64; i += kThreads) sLane[i] = lane_offsets(pd, i >> 6, i & 63, TSP, TANG);
   }
   stage_offsets(pd, sOff, tid);
 
@@ -1403,7 +1449,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       // sequence: only the issue order changes.  Offsets and gate entries are loaded two steps ahead.
       StepRaw rw[2];
       load_step(sOff, sGV, MAXG - 1, ly, lx, true, rw[(MAXG - 1) & 1]);
-      if (MAXG > 1) load_step(sOff, sGV, MAXG > 1 ? MAXG - 2 : 0, ly, lx, true, rw[(MAXG - 2) & 1]);
+      rw[(MAXG - 1) & 1].lanep = sLane[64 * (MAXG - 1) + lane];
+      if (MAXG > 1) {
+        load_step(sOff, sGV, MAXG > 1 ? MAXG - 2 : 0, ly, lx, true, rw[(MAXG - 2) & 1]);
+        rw[(MAXG - 2) & 1].lanep = sLane[64 * (MAXG > 1 ? MAXG - 2 : 0) + lane];
+      }
       R av[16], bx[16];
       WTile<TANG> wy, wx;
       int ad[4];
@@ -1411,9 +1461,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       // LDS bases stay instruction offsets (one add per operand address); per-lane selects on the
       // loaded offsets, wave-uniform parts scalar
       auto env_reads = [&](const StepRaw& st, const GateOff& O) {
-        const int tl = bitsel(sub, 0, st.off[0]) + bitsel(sub, 1, st.off[1]) + bitsel(cidx, 0, st.off[8]) +
-                       bitsel(cidx, 1, st.off[9]) + bitsel(uwave, 0, O.go[6]) + bitsel(uwave, 1, O.go[7]);
-        int eb = (int)sizeof(R) * (lane_scalar_off + 2 * tl);
+        const int wv = bitsel(uwave, 0, O.go[6]) + bitsel(uwave, 1, O.go[7]);
+        int eb = (st.lanep & 0xffff) + 2 * (int)sizeof(R) * wv;
         asm volatile("" : "+v"(eb));
 #pragma unroll
         for (int c = 0; c < 16; ++c) {
@@ -1426,9 +1475,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       };
       // W operands of a gate (the tile addresses ad are kept for the stores)
       auto w_reads = [&](const StepRaw& st, const GateOff& O, bool ab, bool xs) {
-        int tw, ch[4];
-        w_offsets_lane(O, st.off, uwave, lane, tw, ch);
-        tile_addr(tw, ch, ad);
+        int ch[4];
+        w_chains(O, uwave, ch);
+        tile_addr_packed(st.lanep, ch, ad);
         if (ab) wy.load(sY, sY + TSP, ad);
         if (xs) wx.load(sX, sX + TSP, ad);
       };
@@ -1469,7 +1518,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         for (int r = 0; r < 4; ++r) acc[0][r] = 0;
         if (j > 0) {
           env_reads(rw[(j + 1) & 1], On);
-          if (j > 1) load_step(sOff, sGV, j > 1 ? j - 2 : 0, ly, lx, true, rw[j & 1]);   // gate j's are done
+          if (j > 1) {   // gate j's are done
+            load_step(sOff, sGV, j > 1 ? j - 2 : 0, ly, lx, true, rw[j & 1]);
+            rw[j & 1].lanep = sLane[64 * (j > 1 ? j - 2 : 0) + lane];
+          }
         }
       }
     } else {
@@ -1543,7 +1595,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   if constexpr (kF32) {
     if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, tid);   // staged by the last tile, after its barrier
   }
-  env_partials<R, MAXG>(acc, sAcc, (double*)sY, sM, ng, tid, a.env_part);
+  env_partials<R, MAXG>(acc, sAcc, (double*)sY, (double*)sX, ng, tid, a.env_part);   // sX, sY free now
 }
 
 #undef QHVP_FWD_PREFETCH
