@@ -1290,9 +1290,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   constexpr int TSMAX = LD::TSMAX, TSP = LD::TSP;
   constexpr int NST = TANG ? 2 : 1;
   constexpr bool kF32 = std::is_same<R, float>::value;
-  // sX: forward states (psi | dpsi) at the current gate's output, sY: backward states (a | b)
-  __shared__ __attribute__((aligned(16))) T sX[NST * TSP];
-  __shared__ __attribute__((aligned(16))) T sY[NST * TSP];
+  // sX: forward states (psi | dpsi) at the current gate's output, sY: backward states (a | b).
+  // Both start on a 512-byte boundary: the environment operands of sY and sX sit at the same index
+  // of each array, so each pair is one ds_read2st64 (offsets in units of 256 / 512 bytes).
+  __shared__ __attribute__((aligned(512))) T sX[NST * TSP];
+  __shared__ __attribute__((aligned(512))) T sY[NST * TSP];
   __shared__ double sAcc[kF32 ? MAXG * 256 : 1];
   __shared__ int sLane[kF32 ? MAXG * 64 : 1];
   __shared__ __attribute__((aligned(16))) float sStg[kF32 ? 4 * MAXG * 256 : 1];
