@@ -495,27 +495,11 @@ __device__ __forceinline__ void w_offsets(const GateOff& o, int wave, int lane, 
   ch[3] = wv + go[4] + go[5];
 }
 
-// The same, with the per-lane selects reading raw (the offsets as loaded from LDS into vector
-// registers, equal in every lane) instead of their scalar copies: a select between a scalar and 0
-// under a lane mask would first copy the scalar into a vector register.
-__device__ __forceinline__ void w_offsets_lane(const GateOff& o, const int (&raw)[kOffs], int wave, int lane, int& tl,
-                                               int (&ch)[4]) {
-  const int* go = o.go;
-  const int col = lane & 15, g = lane >> 4;
-  tl = bitsel(col, 0, raw[0]) + bitsel(col, 1, raw[1]) + bitsel(col, 2, raw[2]) + bitsel(col, 3, raw[3]) +
-       bitsel(g, 0, raw[8]) + bitsel(g, 1, raw[9]);
-  const int wv = bitsel(wave, 0, go[6]) + bitsel(wave, 1, go[7]);
-  ch[0] = wv;
-  ch[1] = wv + go[4];
-  ch[2] = wv + go[5];
-  ch[3] = wv + go[4] + go[5];
-}
-
 // complex64 per-lane offsets of a pass, computed once per launch (they depend on the gate slot and
 // the lane only): sLane[64 j + l] packs, for lane l and gate slot j, the byte index of the lane's
 // environment operand (low 16 bits; elements of R, second state array included) and 8x the
 // element index of its W-tile element (high 16 bits), both without the wave-uniform parts.
-// Bit-select arithmetic as in w_offsets_lane and the environment operand layout of k_bwd_out.
+// The same bit selects as w_offsets, and the environment operand layout of k_bwd_out.
 __device__ __forceinline__ int lane_offsets(const PassDesc& pd, int j, int l, int tsp, bool tang) {
   const int* go = pd.goff[j];
   const int* ao = pd.aoff[j];
