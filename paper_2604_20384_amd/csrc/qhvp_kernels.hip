@@ -852,10 +852,12 @@ __global__ void __launch_bounds__(kThreads)
 
 // complex64 environment accumulation.  A wave's FP32 MFMA accumulator holds one tile's partial sums
 // of one gate slot (64 products per element); right after its step the wave stages it in LDS
-// (stg[(w * MAXG + j) * 256 + 4 * lane + r]), so no accumulator outlives its step.  Between the
-// end of that tile and the next tile's first barrier every thread adds the four waves' values of
-// its own element e = 4 * lane + r, in wave order and in FP64, into one FP64 running sum per gate
-// slot (sAcc[j * 256 + e]): the workgroup keeps 256 doubles per gate.
+// (stg[(w * MAXG + j) * 256 + 4 * lane + r]), so no accumulator outlives its step.  k_bwd reduces
+// after every tile, k_bwd_out after every pair of tiles (the second adds its partial to the first's
+// in FP32: 128 products per element).  Between the end of that tile (pair) and the next tile's
+// first barrier every thread adds the four waves' values of its own element e = 4 * lane + r, in
+// wave order and in FP64, into one FP64 running sum per gate slot (sAcc[j * 256 + e]): the
+// workgroup keeps 256 doubles per gate.
 template <int MAXG>
 __device__ __forceinline__ void env_put(const Mfma<float>::acc_t& e, float* stg, int j, int tid) {
   const int wave = tid >> 6, lane = tid & 63;
@@ -863,6 +865,18 @@ __device__ __forceinline__ void env_put(const Mfma<float>::acc_t& e, float* stg,
 }
 // All MAXG slots are reduced, used or not (an unused slot's sum is never read): without a branch
 // per slot the loads of every slot are in flight together.
+// The same, added to what the wave staged for the previous tile: k_bwd_out stages the sum of a pair
+// of tiles (128 products per element in FP32) before the FP64 reduction.
+template <int MAXG>
+__device__ __forceinline__ void env_put_add(const Mfma<float>::acc_t& e, float* stg, int j, int tid) {
+  const int wave = tid >> 6, lane = tid & 63;
+  qv4f* p = (qv4f*)(stg + (wave * MAXG + j) * 256 + 4 * lane);
+  const qv4f prev = *p;
+  qv4f sum;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) sum[r] = prev[r] + e[r];
+  *p = sum;
+}
 template <int MAXG>
 __device__ __forceinline__ void env_reduce(const float* stg, double* sAcc, int tid) {
   double v[MAXG], acc[MAXG];
@@ -1417,9 +1431,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
     }
     if constexpr (kF32) {
-      // the previous tile's staged partials (staged before its final barrier; this tile stages after
-      // the next one)
-      if (it > it0) env_reduce<MAXG>(sStg, sAcc, tid);
+      // the staged partials of the previous pair of tiles (staged before the pair's final barrier;
+      // odd-numbered tiles of the workgroup add to what their predecessor staged)
+      if (it > it0 && ((it - it0) & 1) == 0) env_reduce<MAXG>(sStg, sAcc, tid);
     }
     __syncthreads();
     if (common && it + 1 < it1) QHVP_BWD_PREFETCH(sn, xn);
@@ -1499,7 +1513,8 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         pin16(bx);
 #pragma unroll
         for (int c = 0; c < 16; ++c) acc[0] = M::step(av[c], bx[c], acc[0]);
-        env_put<MAXG>(acc[0], sStg, j, tid);
+        if ((it - it0) & 1) env_put_add<MAXG>(acc[0], sStg, j, tid);
+        else env_put<MAXG>(acc[0], sStg, j, tid);
 #pragma unroll
         for (int r = 0; r < 4; ++r) acc[0][r] = 0;
         if (j > 0) {
@@ -1579,7 +1594,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
   }
   if constexpr (kF32) {
-    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, tid);   // staged by the last tile, after its barrier
+    if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, tid);   // staged by the last one or two tiles, after their barrier
   }
   env_partials<R, MAXG>(acc, sAcc, (double*)sY, (double*)sX, ng, tid, a.env_part);   // sX, sY free now
 }
