@@ -156,22 +156,50 @@ int lds_at(int t, int elem_bytes) {
   return t + (t >> 4);
 }
 
-// 2-adic valuation of x mod 32 (5 for x = 0 mod 32).  Five offsets whose valuations are 0..4 give
-// 32 distinct subset sums mod 32, i.e. distinct banks for the lanes they index.
-int val32(int x) {
-  x &= 31;
-  if (x == 0) return 5;
-  int v = 0;
-  while (!(x & 1)) { x >>= 1; ++v; }
-  return v;
-}
-bool spans32(int a, int b, int c, int d, int e) {
-  int seen = 0;
-  for (int v : {val32(a), val32(b), val32(c), val32(d), val32(e)}) {
-    if (v == 5 || (seen >> v & 1)) return false;
-    seen |= 1 << v;
+// gfx950 LDS bank model, fitted to the hardware's bank-conflict counter on probe access patterns:
+// a wave's access of `width` bytes per lane is served a group of lanes at a time (32-bit: 32 lanes
+// over 32 banks of 4 bytes; 64-bit reads: 32 lanes over 64 banks; 64-bit writes: 16 lanes over 32
+// banks; 128-bit reads: 16 lanes over 64 banks; 128-bit writes: 8 lanes over 32 banks), and a group
+// takes as many cycles as its most used bank holds distinct dwords.  Returns the wave's cycles.
+int lds_cycles(const int (&addr)[64], int width, bool write) {
+  int group = 32, banks = 32;
+  if (width == 8) { group = write ? 16 : 32; banks = write ? 32 : 64; }
+  if (width == 16) { group = write ? 8 : 16; banks = write ? 32 : 64; }
+  int total = 0;
+  for (int s = 0; s < 64; s += group) {
+    int dw[64 * 4], n = 0;
+    for (int l = s; l < s + group; ++l)
+      for (int k = 0; k < width / 4; ++k) dw[n++] = addr[l] / 4 + k;
+    std::sort(dw, dw + n);
+    n = (int)(std::unique(dw, dw + n) - dw);
+    int cnt[64] = {0}, worst = 0;
+    for (int i = 0; i < n; ++i) worst = std::max(worst, ++cnt[dw[i] % banks]);
+    total += worst;
   }
-  return true;
+  return total;
+}
+
+// Modelled bank-conflict cycles of one complex64 backward gate step (k_bwd_out) for a gate on tile
+// bits lo, hi whose group bits 0..3 sit on tile bits p0..p3: the environment operand reads (32-bit,
+// 32 wave accesses per step; lanes over the amplitude bits lo, hi, the state arrays, real / imaginary
+// part and group bits 0, 1) and the W-tile reads and writes (64-bit, 16 each; lanes over group bits
+// 0..3 and lo, hi).  Wave-uniform parts of the addresses shift every lane alike and drop out.
+int c64_step_conflicts(int lo, int hi, int p0, int p1, int p2, int p3) {
+  auto O = [](int b) { return lds_at(1 << b, 8); };
+  auto sel = [](int v, int bit, int off) { return ((v >> bit) & 1) ? off : 0; };
+  int env[64], w[64];
+  for (int l = 0; l < 64; ++l) {
+    const int comp = l & 15, sub = l >> 4;
+    const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
+    const int tl = sel(sub, 0, O(p0)) + sel(sub, 1, O(p1)) + sel(cidx, 0, O(lo)) + sel(cidx, 1, O(hi));
+    env[l] = 4 * (2 * cst * qhvp::kTspC64 + cri + 2 * tl);
+    const int col = l & 15, g = l >> 4;
+    const int tw = sel(col, 0, O(p0)) + sel(col, 1, O(p1)) + sel(col, 2, O(p2)) + sel(col, 3, O(p3)) +
+                   sel(g, 0, O(lo)) + sel(g, 1, O(hi));
+    w[l] = 8 * tw;
+  }
+  return 32 * (lds_cycles(env, 4, false) - 2) + 16 * (lds_cycles(w, 8, false) - 2) +
+         16 * (lds_cycles(w, 8, true) - 4);
 }
 
 // Per-pass constants of the kernels' tile addressing: the tile-enumeration mask and, per gate, the
@@ -203,23 +231,19 @@ void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
           if (b != lo && b != hi && b != f0 && b != f1) avail[k++] = b;
         for (int i = 0; i < 6; ++i) pos[i] = avail[i];
         if (elem_bytes == 8) {
-          // complex64: choose the group bits the lanes run over (bits 0..3: the 16 columns of the
-          // gate application, bits 0..1: the sub-rows of the environment operands) so that both
-          // access patterns hit distinct banks: gate application over {bits 0..3, tlo}, environment
-          // over {tlo, thi, second state array, bits 0..1}
-          auto O = [&](int b) { return lds_at(1 << b, elem_bytes); };
+          // complex64: choose the tile bits the lanes run over (group bits 0, 1: the sub-rows of
+          // the environment operands; 0..3: the 16 columns of the gate application; the order of
+          // 2 and 3 does not matter) with the fewest modelled bank-conflict cycles per gate step
           int best = -1;
-          for (int a0 = 0; a0 < 6 && best < 2; ++a0)
-            for (int a1 = 0; a1 < 6 && best < 2; ++a1)
-              for (int a2 = 0; a2 < 6 && best < 2; ++a2)
-                for (int a3 = 0; a3 < 6 && best < 2; ++a3) {
-                  if (a0 == a1 || a0 == a2 || a0 == a3 || a1 == a2 || a1 == a3 || a2 == a3) continue;
-                  const int p0 = avail[a0], p1 = avail[a1], p2 = avail[a2], p3 = avail[a3];
-                  const int score = (spans32(O(lo), O(hi), qhvp::kTspC64, O(p0), O(p1)) ? 1 : 0) +
-                                    (spans32(O(p0), O(p1), O(p2), O(p3), O(lo)) ? 1 : 0);
-                  if (score > best) {
-                    best = score;
-                    pos[0] = p0; pos[1] = p1; pos[2] = p2; pos[3] = p3;
+          for (int a0 = 0; a0 < 6; ++a0)
+            for (int a1 = 0; a1 < 6; ++a1)
+              for (int a2 = 0; a2 < 6; ++a2)
+                for (int a3 = a2 + 1; a3 < 6; ++a3) {
+                  if (a0 == a1 || a0 == a2 || a0 == a3 || a1 == a2 || a1 == a3) continue;
+                  const int c = c64_step_conflicts(lo, hi, avail[a0], avail[a1], avail[a2], avail[a3]);
+                  if (best < 0 || c < best) {
+                    best = c;
+                    pos[0] = avail[a0]; pos[1] = avail[a1]; pos[2] = avail[a2]; pos[3] = avail[a3];
                     int r = 4;
                     for (int i = 0; i < 6; ++i)
                       if (i != a0 && i != a1 && i != a2 && i != a3) pos[r++] = avail[i];
