@@ -53,3 +53,27 @@ def test_plan_rejects_bad_shapes():
     assert _lib.lib.qhvp_plan(1, 3, 0, None, None) < 0
     assert _lib.lib.qhvp_plan(31, 3, 0, None, None) < 0
     assert _lib.lib.qhvp_plan(20, 20, 3, (_lib.C.c_int * 3)(), None) < 0
+
+
+def _header_constants():
+    """kLdsPadC64 / kTspC64 / kMaxTileBits as written in the kernels' shared header."""
+    import os
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "paper_2604_20384_amd", "csrc", "qhvp_internal.h")).read()
+    pads = [int(x) for x in re.search(r"kLdsPadC64\[kMaxTileBits\]\s*=\s*\{([^}]*)\}", text).group(1).split(",")]
+    tsp = int(re.search(r"constexpr int kTspC64\s*=\s*(\d+);", text).group(1))
+    bits = int(re.search(r"constexpr int kMaxTileBits\s*=\s*(\d+);", text).group(1))
+    return pads, tsp, bits
+
+
+def test_complex64_lds_layout_is_one_to_one():
+    """The padded complex64 tile layout must give every tile element its own LDS slot below the
+    second state array's offset, leave bits 0..4 unpadded (the 8- and 16-byte tile transfers read
+    consecutive elements) and keep slot 32 free for the kernels' dummy writes of small tiles."""
+    pads, tsp, bits = _header_constants()
+    assert len(pads) == bits and pads[:5] == [0] * 5
+    at = [t + sum(pads[b] for b in range(bits) if t >> b & 1) for t in range(1 << bits)]
+    assert len(set(at)) == len(at)
+    assert max(at) < tsp
+    assert 32 not in at
