@@ -19,14 +19,16 @@ constexpr int kMaxQubits = 30;
 constexpr int kThreads = 256;     // 4 wave64s; one 4-amplitude group per thread per gate at mb = 10
 constexpr int kEnvVals = 64;      // 16 complex E + 16 complex D per gate, as 64 doubles
 
-// complex64 LDS tile layout (8-byte elements; gfx950 LDS: 64 banks of 4 bytes): tile element t sits
-// at t + sum of kLdsPadC64[b] over the set bits b of t, i.e. tile bit b at element offset
-// 2^b + kLdsPadC64[b] = 1, 2, 4, 8, 16, 33, 68, 136, 272, 552.  The offsets' residues mod 32 let the
-// kernels' lane patterns (16 lanes over 4 group bits plus a gate bit; 32 lanes over two gate bits,
-// two group bits and the second state array) hit distinct banks for almost every gate.  Each state
-// array spans kTspC64 elements (the extent 1093, rounded to a residue of the same class).
-constexpr int kLdsPadC64[kMaxTileBits] = {0, 0, 0, 0, 0, 1, 4, 8, 16, 40};
-constexpr int kTspC64 = 1094;
+// complex64 LDS tile layout (8-byte elements): tile element t sits at t + sum of kLdsPadC64[b] over
+// the set bits b of t, i.e. tile bit b at element offset 2^b + kLdsPadC64[b] = 1, 2, 4, 8, 16, 34,
+// 68, 136, 270, 552 (one-to-one on the 1024 elements, extent 1092; index 32 stays free for the
+// kernels' dummy slot), and the second state array kTspC64 elements after the first.  The pads and
+// kTspC64 minimise, under the measured LDS bank model (32-bit accesses: 32 lanes over 32 banks;
+// 64-bit reads: 32 lanes over 64 banks; 64-bit writes: 16 lanes over 32 banks), the conflict cycles
+// of a backward gate step with the host's per-gate choice of lane bits at n = 20, plus those of the
+// tile puts and reads.
+constexpr int kLdsPadC64[kMaxTileBits] = {0, 0, 0, 0, 0, 2, 4, 8, 14, 40};
+constexpr int kTspC64 = 1093;
 
 struct PassDesc {
   int n;      // qubits

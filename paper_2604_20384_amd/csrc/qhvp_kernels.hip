@@ -166,7 +166,8 @@ __device__ __forceinline__ void apply_wdag(cptr<decltype(T::x)> G, cptr<decltype
 // (used to split MFMA operand addresses into a per-lane and a wave-uniform part), and leave index
 // DUMMY unused (a sink for writes of elements beyond a tile of fewer than 2^kMaxTileBits).
 template <typename T> struct Lds;
-// complex64: per-bit offsets chosen against the 64 banks (kLdsPadC64); TSP elements per state array.
+// complex64: per-bit offsets chosen under the measured bank model (kLdsPadC64); TSP elements per
+// state array.
 template <> struct Lds<float2> {
   static constexpr int TSMAX = 1 << kMaxTileBits;
   static constexpr int TSP = kTspC64;
