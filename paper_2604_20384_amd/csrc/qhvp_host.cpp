@@ -56,9 +56,13 @@ int num_gates(int n, int L) {
 // is greedy: each pass takes the window that admits the most gates (scanning gates in index order,
 // so a gate may join once the gates it follows are done or already in the pass), and - at full
 // tile size - at most mb - 2 touched tile bits, so that two untouched bits index the waves and the
-// pass runs without workgroup barriers (wave-local).  Gates of several layers share a pass, which
-// cuts the number of HBM round trips (n=20, L=20: 40 passes for 190 gates; one layer per pass
-// would need 60).  gates_before[q] = gates in the passes before q (np + 1 entries).
+// pass runs without workgroup barriers (wave-local).  In the plan's tail (at most kTailGates gates
+// left) each window is instead scored by the passes a greedy plan of the rest would then need
+// (ties: more gates now), which lets the last passes merge.  Gates of several layers share a pass,
+// which cuts the number of HBM round trips (n=20, L=20: 32 passes for 190 gates, the fewest at 6
+// gates per pass; one layer per pass would need 60).  gates_before[q] = gates in the passes before
+// q (np + 1 entries).
+constexpr int kTailGates = 48;
 std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* gates_before) {
   const int K = num_gates(n, L);
   std::vector<int> glo(K), glayer(K);
@@ -93,31 +97,72 @@ std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* gates_b
   const int max_touched = mb == qhvp::kMaxTileBits ? mb - 2 : mb;
 
   std::vector<qhvp::PassDesc> passes;
-  std::vector<char> done(K, 0), in_pass(K, 0);
+  std::vector<char> done(K, 0);
+  // the gates a pass over tile bits `bits` takes, greedily in gate index order
+  auto take_for = [&](const std::vector<int>& bits, const std::vector<char>& dn, std::vector<int>& take) {
+    std::vector<char> in_tile(n, 0), touched(n, 0), in_pass(K, 0);
+    for (int b : bits) in_tile[b] = 1;
+    take.clear();
+    int nt = 0;
+    for (int k = 0; k < K && (int)take.size() < qhvp::kMaxGates; ++k) {
+      if (dn[k] || !in_tile[glo[k]] || !in_tile[glo[k] + 1]) continue;
+      bool ready = true;
+      for (int d : deps[k]) ready = ready && (dn[d] || in_pass[d]);
+      if (!ready) continue;
+      const int add = (touched[glo[k]] ? 0 : 1) + (touched[glo[k] + 1] ? 0 : 1);
+      if (nt + add > max_touched) continue;
+      touched[glo[k]] = touched[glo[k] + 1] = 1;
+      nt += add;
+      in_pass[k] = 1;
+      take.push_back(k);
+    }
+  };
+  // the window a greedy pass takes (most gates, the first such window)
+  auto greedy_pick = [&](const std::vector<char>& dn, std::vector<int>& best, std::vector<int>& best_bits) {
+    std::vector<int> take;
+    best.clear();
+    for (const auto& bits : cands) {
+      take_for(bits, dn, take);
+      if (take.size() > best.size()) { best = take; best_bits = bits; }
+    }
+  };
+  // passes a greedy plan needs for the gates not in dn
+  auto greedy_count = [&](std::vector<char> dn, int left) {
+    int np = 0;
+    std::vector<int> best, best_bits;
+    while (left > 0) {
+      greedy_pick(dn, best, best_bits);
+      if (best.empty()) return 1 << 20;   // (cannot happen: the first pending gate always fits)
+      for (int k : best) dn[k] = 1;
+      left -= (int)best.size();
+      ++np;
+    }
+    return np;
+  };
   if (gates_before) gates_before->assign(1, 0);
   int remaining = K, total = 0;
   while (remaining > 0) {
     std::vector<int> best, best_bits;
-    for (const auto& bits : cands) {
-      std::vector<char> in_tile(n, 0), touched(n, 0);
-      for (int b : bits) in_tile[b] = 1;
+    if (remaining > kTailGates) {
+      greedy_pick(done, best, best_bits);
+    } else {
+      int best_cost = -1;
       std::vector<int> take;
-      int nt = 0;
-      for (int k = 0; k < K && (int)take.size() < qhvp::kMaxGates; ++k) {
-        if (done[k] || !in_tile[glo[k]] || !in_tile[glo[k] + 1]) continue;
-        bool ready = true;
-        for (int d : deps[k]) ready = ready && (done[d] || in_pass[d]);
-        if (!ready) continue;
-        const int add = (touched[glo[k]] ? 0 : 1) + (touched[glo[k] + 1] ? 0 : 1);
-        if (nt + add > max_touched) continue;
-        touched[glo[k]] = touched[glo[k] + 1] = 1;
-        nt += add;
-        in_pass[k] = 1;
-        take.push_back(k);
+      for (const auto& bits : cands) {
+        take_for(bits, done, take);
+        if (take.empty()) continue;
+        std::vector<char> dn = done;
+        for (int k : take) dn[k] = 1;
+        const int cost = 1 + greedy_count(dn, remaining - (int)take.size());
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && take.size() > best.size())) {
+          best_cost = cost;
+          best = take;
+          best_bits = bits;
+        }
       }
-      for (int k : take) in_pass[k] = 0;
-      if (take.size() > best.size()) { best = take; best_bits = bits; }
+      if (best.empty()) greedy_pick(done, best, best_bits);
     }
+    if (best.empty()) break;   // (cannot happen: the first pending gate always fits a window)
     qhvp::PassDesc pd;
     std::memset(&pd, 0, sizeof(pd));
     pd.n = n;

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 CASES = [  # (n, L, N_s, gate counts its ansatz plan must contain)
     (2, 1, 3, {1}), (6, 3, 3, {2, 6}), (2, 5, 3, {3}), (2, 7, 3, {4}), (2, 9, 3, {5}),
-    (11, 5, 2, {1, 5, 6}), (13, 5, 2, {2, 4, 6}), (12, 7, 2, {3, 6}),
+    (13, 11, 2, {1, 5, 6}), (13, 3, 2, {2, 4, 6}), (12, 7, 2, {3, 6}),
 ]
 
 

@@ -29,9 +29,12 @@ def test_plan_is_a_dependency_respecting_permutation(n, L):
 
 
 def test_plan_sizes():
-    """Several layers per pass: n=20, L=20 (190 gates) takes 33 passes; one layer per pass would need 60."""
+    """Several layers per pass: n=20, L=20 (190 gates) takes 32 passes, the fewest at 6 gates per pass
+    (one layer per pass would need 60); n=16, L=12 (90 gates) takes 15, also the fewest."""
     per, _ = _plan(20, 20)
-    assert len(per) == 33
+    assert len(per) == 32 and sum(per) == 190 and max(per) <= 6
+    per, _ = _plan(16, 12)
+    assert len(per) == 15 and sum(per) == 90
 
 
 @pytest.mark.parametrize("n,L", [(7, 6), (10, 5)])
