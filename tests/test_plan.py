@@ -28,6 +28,25 @@ def test_plan_is_a_dependency_respecting_permutation(n, L):
                 assert when[k2] < when[k], (n, L, k, k2)
 
 
+@pytest.mark.parametrize("n,L", [(10, 6), (12, 5), (16, 12), (20, 20), (23, 6)])
+def test_plan_passes_fit_wave_local_tiles(n, L):
+    """Full tiles (n >= 10): a pass spans the 4 coalesced low statevector bits plus one window of 6
+    consecutive bits, and touches at most 8 of those 10, so that two untouched tile bits can index
+    the waves (wave-local passes).  Gate k on qubits (q, q+1) acts on bits n-2-q and n-1-q."""
+    per, order = _plan(n, L)
+    pos = circuit.brickwall_positions(n, L)
+    i = 0
+    for c in per:
+        bits = set()
+        for k in order[i:i + c]:
+            q = pos[k][1]
+            bits |= {n - 2 - q, n - 1 - q}
+        i += c
+        assert len(bits) <= 8, (n, L, sorted(bits))
+        high = sorted(b for b in bits if b >= 4)
+        assert not high or high[-1] - high[0] < 6, (n, L, sorted(bits))
+
+
 def test_plan_sizes():
     """Several layers per pass: n=20, L=20 (190 gates) takes 32 passes, the fewest at 6 gates per pass
     (one layer per pass would need 60); n=16, L=12 (90 gates) takes 15, also the fewest."""
