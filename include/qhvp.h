@@ -35,7 +35,14 @@
  *
  * Errors: every entry point returns a qhvp_status, never aborts, and leaves
  * its outputs untouched on error; qhvp_last_error() gives a message (per
- * thread).  Arguments are validated before any device work is launched.
+ * thread).  Arguments are validated before any device work is launched.  The
+ * device-pointer calls (*_dev) validate pointers and sizes on the host and the
+ * values of G and V on the device: an invalid value leaves every output of the
+ * call untouched and sets the problem's device status (qhvp_device_status).
+ *
+ * Host and device calls run the same device code: the host calls copy G and V
+ * to the device, enqueue the device-pointer path and copy its outputs back, so
+ * their results are bitwise those of the corresponding *_dev call.
  *
  * Threading: one problem is used by one host thread at a time; calls on one
  * problem are serialised on its stream.  Different problems (each on its
@@ -126,23 +133,53 @@ void qhvp_problem_destroy(qhvp_problem* p);
 /* Cost C and fidelity F for gates G (K*16 complex, host).  One forward sweep (Sec. III, single-pass overlap). */
 qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fidelity);
 
-/* Backward sweep algorithm (gradient and HVP calls).  When every gate satisfies
- * |G_k|_F |G_k^-1|_F <= 8 (unitary gates: 4), each backward pass starts from the forward states at
- * the pass OUTPUT and undoes the gates on them (psi <- G^-1 psi, dpsi <- G^-1 dpsi - G^-1 V G^-1 psi)
- * while it undoes them on the backward states; the environments taken against output states are
- * mapped back on the host in FP64 (E = Et G^-T, D = (Dt - E V^T) G^-T).  Otherwise, or when the
+/* Backward sweep algorithm (gradient and HVP calls), chosen on the device for each call.  When every
+ * gate satisfies |G_k|_F |G_k^-1|_F <= 8 (unitary gates: 4), each backward pass starts from the
+ * forward states at the pass OUTPUT and undoes the gates on them (psi <- G^-1 psi, dpsi <- G^-1 dpsi -
+ * G^-1 V G^-1 psi) while it undoes them on the backward states; the environments taken against
+ * output states are mapped back in FP64 (E = Et G^-T, D = (Dt - E V^T) G^-T).  Otherwise, or when the
  * environment variable QHVP_BACKWARD is "recompute", each pass recomputes the forward states
  * inside the tile from the pass input.  Both give the same sums up to rounding. */
 
-/* Cost and gradient (K*16 complex, host) of C at G: forward sweep, then the backward
- * sweep accumulating the environments (Eq. environment, Alg. 2 "postprocess gradient"). */
+/* Cost, fidelity F = 1 - C and gradient (K*16 complex, host) of C at G: forward sweep, then the
+ * backward sweep accumulating the environments (Eq. environment, Alg. 2 "postprocess gradient").
+ * cost and fidelity may be NULL.  F is returned as computed (not as 1 - C, which cancels when F is
+ * small). */
 qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom,
-                      double* cost, double* grad);
+                      double* cost, double* fidelity, double* grad);
 
-/* Cost, gradient and HVP H(C)[V] (each K*16 complex, host) at G along V (K*16
- * complex, host): Alg. 1 + Alg. 2 with tangent states. `grad` may be NULL. */
+/* Cost, fidelity, gradient and HVP H(C)[V] (each K*16 complex, host) at G along V (K*16
+ * complex, host): Alg. 1 + Alg. 2 with tangent states. cost, fidelity and grad may be NULL. */
 qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom,
-                     double* cost, double* grad, double* hvp);
+                     double* cost, double* fidelity, double* grad, double* hvp);
+
+/* ---- device-pointer calls (the same evaluations with G, V and the outputs in device memory) ----
+ * d_G, d_V: K*16 complex FP64 (interleaved re, im; 2*K*16 doubles), device memory of the problem's
+ * device, read during the call's device work only; outputs: device doubles (cost, fidelity: one
+ * each; grad, hvp: K*16 complex), written by the call's last kernel.  The calls enqueue their work on
+ * the problem's stream and return without waiting; the caller orders later use of the outputs after
+ * that stream (a torch stream passed at problem creation does this for torch work on the same
+ * stream).  Host-side errors (NULL or non-device pointers, sizes, a problem without tangent storage)
+ * return before anything is enqueued.  Non-finite entries of G or V, or (Riemannian) gates off the
+ * unitary manifold, are detected on the device: the call then writes none of its outputs and
+ * qhvp_device_status reports the reason.  Cost, gradient and HVP follow Alg. 1 + Alg. 2 over the
+ * samples (Eq. costHS); Riemannian outputs follow App. F with V projected first. */
+qhvp_status qhvp_cost_dev(qhvp_problem* p, const double* d_G, double* d_cost, double* d_fidelity);
+qhvp_status qhvp_grad_dev(qhvp_problem* p, const double* d_G, qhvp_geometry geom, double* d_cost,
+                          double* d_fidelity, double* d_grad);
+qhvp_status qhvp_hvp_dev(qhvp_problem* p, const double* d_G, const double* d_V, qhvp_geometry geom,
+                         double* d_cost, double* d_fidelity, double* d_grad, double* d_hvp);
+/* Two-phase form on device pointers (as qhvp_forward / qhvp_backward below); d_cost, d_fidelity,
+ * d_grad may be NULL. */
+qhvp_status qhvp_forward_dev(qhvp_problem* p, const double* d_G, const double* d_V, qhvp_geometry geom,
+                             double* d_cost, double* d_fidelity);
+qhvp_status qhvp_backward_dev(qhvp_problem* p, double* d_grad, double* d_hvp);
+
+/* Device-side input check of the last call (waits for the problem's stream): 0 if its inputs were
+ * valid, else an OR of QHVP_DEV_NONFINITE and QHVP_DEV_NOT_UNITARY. */
+#define QHVP_DEV_NONFINITE 1    /* a non-finite entry in G or V */
+#define QHVP_DEV_NOT_UNITARY 2  /* Riemannian geometry with |G_k^dag G_k - I|_F > 1e-10 for some k */
+qhvp_status qhvp_device_status(qhvp_problem* p, int* status);
 
 /* Fixed-G reuse and several directions (Sec. IV: the truncated-CG inner loop takes many HVPs at
  * one point; App. G: one HVP per tangent basis vector).  The forward states psi that a gradient or

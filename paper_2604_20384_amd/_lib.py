@@ -54,8 +54,14 @@ _SIGS = {
                                       C.c_int, _vp, C.c_size_t, _vp, C.POINTER(_vp)]),
     "qhvp_problem_destroy": (None, [_vp]),
     "qhvp_cost": (C.c_int, [_vp, _dp, _dp, _dp]),
-    "qhvp_grad": (C.c_int, [_vp, _dp, C.c_int, _dp, _dp]),
-    "qhvp_hvp": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp, _dp]),
+    "qhvp_grad": (C.c_int, [_vp, _dp, C.c_int, _dp, _dp, _dp]),
+    "qhvp_hvp": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp, _dp, _dp]),
+    "qhvp_cost_dev": (C.c_int, [_vp, _vp, _vp, _vp]),
+    "qhvp_grad_dev": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _vp]),
+    "qhvp_hvp_dev": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),
+    "qhvp_forward_dev": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp, _vp]),
+    "qhvp_backward_dev": (C.c_int, [_vp, _vp, _vp]),
+    "qhvp_device_status": (C.c_int, [_vp, _ip]),
     "qhvp_hvp_batch": (C.c_int, [_vp, _dp, C.c_int, _dp, C.c_int, _dp, _dp, _dp]),
     "qhvp_states_kept_for": (C.c_int, [_vp, _dp]),
     "qhvp_forward": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp]),

@@ -2,8 +2,10 @@
 
 Device memory for the workspace comes from PyTorch (so its peak HBM is
 visible to `torch.cuda.max_memory_allocated`), and the HIP stream is a torch
-stream; everything else is marshalling.  Arrays are numpy complex128 of
-shape (K, 4, 4) for gates / directions / results.
+stream; everything else is marshalling.  Host calls take and return numpy
+complex128 arrays of shape (K, 4, 4); the *_dev calls take and return torch
+complex128 tensors on the problem's device and run asynchronously on the
+problem's stream (no host copy of G, V or the results).
 """
 from __future__ import annotations
 
@@ -145,26 +147,104 @@ class Problem:
         G = _c128(G, (self.K, 4, 4))
         c, f = C.c_double(), C.c_double()
         check(lib.qhvp_cost(self.handle, dptr(_f64(G)), C.byref(c), C.byref(f)))
+        self.last_fidelity = f.value
         return c.value, f.value
 
     def grad(self, G, riemannian=False):
+        """(cost, gradient); the fidelity F of the call (as computed, not 1 - cost) is in
+        `last_fidelity`."""
         self.epoch += 1
         G = _c128(G, (self.K, 4, 4))
         g = np.empty((self.K, 4, 4), dtype=np.complex128)
-        c = C.c_double()
-        check(lib.qhvp_grad(self.handle, dptr(_f64(G)), int(riemannian), C.byref(c), dptr(_f64(g))))
+        c, f = C.c_double(), C.c_double()
+        check(lib.qhvp_grad(self.handle, dptr(_f64(G)), int(riemannian), C.byref(c), C.byref(f), dptr(_f64(g))))
+        self.last_fidelity = f.value
         return c.value, g
 
     def hvp(self, G, V, riemannian=False):
+        """(cost, gradient, HVP along V); the call's fidelity is in `last_fidelity`."""
         self.epoch += 1
         G = _c128(G, (self.K, 4, 4))
         V = _c128(V, (self.K, 4, 4))
         g = np.empty((self.K, 4, 4), dtype=np.complex128)
         h = np.empty((self.K, 4, 4), dtype=np.complex128)
-        c = C.c_double()
-        check(lib.qhvp_hvp(self.handle, dptr(_f64(G)), dptr(_f64(V)), int(riemannian), C.byref(c),
+        c, f = C.c_double(), C.c_double()
+        check(lib.qhvp_hvp(self.handle, dptr(_f64(G)), dptr(_f64(V)), int(riemannian), C.byref(c), C.byref(f),
                            dptr(_f64(g)), dptr(_f64(h))))
+        self.last_fidelity = f.value
         return c.value, g, h
+
+    # ---- device-pointer calls on torch tensors (complex128, shape (K, 4, 4), on the problem's device)
+    def _dev_in(self, t, name):
+        import torch
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or t.shape != (self.K, 4, 4):
+            raise ValueError(f"{name} must be a complex128 torch tensor of shape ({self.K}, 4, 4)")
+        if t.device != torch.device(f"cuda:{self.device}"):
+            raise ValueError(f"{name} must be on cuda:{self.device}")
+        return t.contiguous()
+
+    def _dev_out(self, n_mats):
+        import torch
+        dev = f"cuda:{self.device}"
+        scal = torch.empty(2, dtype=torch.float64, device=dev)
+        mats = [torch.empty((self.K, 4, 4), dtype=torch.complex128, device=dev) for _ in range(n_mats)]
+        return scal, mats
+
+    def cost_dev(self, G):
+        """(cost, fidelity) as 0-dim float64 device tensors, enqueued on the problem's stream."""
+        self.epoch += 1
+        G = self._dev_in(G, "G")
+        scal, _ = self._dev_out(0)
+        check(lib.qhvp_cost_dev(self.handle, G.data_ptr(), scal.data_ptr(), scal.data_ptr() + 8))
+        self._dev_keep = (G,)   # alive until the enqueued work has read it
+        return scal[0], scal[1]
+
+    def grad_dev(self, G, riemannian=False):
+        """(cost, fidelity, gradient) as device tensors; G never leaves the device."""
+        self.epoch += 1
+        G = self._dev_in(G, "G")
+        scal, (g,) = self._dev_out(1)
+        check(lib.qhvp_grad_dev(self.handle, G.data_ptr(), int(riemannian), scal.data_ptr(), scal.data_ptr() + 8,
+                                g.data_ptr()))
+        self._dev_keep = (G,)
+        return scal[0], scal[1], g
+
+    def hvp_dev(self, G, V, riemannian=False):
+        """(cost, fidelity, gradient, HVP along V) as device tensors."""
+        self.epoch += 1
+        G, V = self._dev_in(G, "G"), self._dev_in(V, "V")
+        scal, (g, h) = self._dev_out(2)
+        check(lib.qhvp_hvp_dev(self.handle, G.data_ptr(), V.data_ptr(), int(riemannian), scal.data_ptr(),
+                               scal.data_ptr() + 8, g.data_ptr(), h.data_ptr()))
+        self._dev_keep = (G, V)
+        return scal[0], scal[1], g, h
+
+    def forward_dev(self, G, V=None, riemannian=False):
+        """Forward sweep on device tensors (keeps the checkpoints for one `backward_dev`);
+        returns (cost, fidelity) as device tensors."""
+        self.epoch += 1
+        G = self._dev_in(G, "G")
+        Vd = None if V is None else self._dev_in(V, "V")
+        scal, _ = self._dev_out(0)
+        check(lib.qhvp_forward_dev(self.handle, G.data_ptr(), None if Vd is None else Vd.data_ptr(),
+                                   int(riemannian), scal.data_ptr(), scal.data_ptr() + 8))
+        self._fwd_tangent = V is not None
+        self._dev_keep = (G, Vd)   # the inputs stay alive until the enqueued sweep has read them
+        return scal[0], scal[1]
+
+    def backward_dev(self):
+        """Backward sweep of the last `forward_dev`: grad, or (grad, hvp), as device tensors."""
+        self.epoch += 1
+        tang = getattr(self, "_fwd_tangent", False)
+        _, mats = self._dev_out(2 if tang else 1)
+        check(lib.qhvp_backward_dev(self.handle, mats[0].data_ptr(), mats[1].data_ptr() if tang else None))
+        return mats[0] if not tang else (mats[0], mats[1])
+
+    def device_status(self) -> int:
+        """Device-side input check of the last call (waits for the stream): 0 if valid."""
+        st = C.c_int()
+        check(lib.qhvp_device_status(self.handle, C.byref(st)))
+        return st.value
 
     def hvp_batch(self, G, Vs, riemannian=False):
         """HVPs at one G along several directions Vs (M, K, 4, 4) -> (cost, grad, (M, K, 4, 4)).
@@ -200,6 +280,7 @@ class Problem:
         c, f = C.c_double(), C.c_double()
         check(lib.qhvp_forward(self.handle, dptr(_f64(G)), Vp, int(riemannian), C.byref(c), C.byref(f)))
         self._fwd_tangent = V is not None
+        self.last_fidelity = f.value
         return c.value, f.value
 
     def backward(self):

@@ -11,10 +11,12 @@ convention of PyTorch's complex `.grad`.
 A problem holds the checkpoints of one forward sweep at a time: if it was used for anything
 else between this function's forward and backward, the backward re-runs the forward sweep
 first (same result, bitwise).
+
+Both directions use the library's device-pointer calls: G, the cost and the gradient stay on the
+device (on the problem's stream), with no host copy of the gates.
 """
 from __future__ import annotations
 
-import numpy as np
 import torch
 
 from .api import Problem
@@ -25,19 +27,19 @@ class HSCost(torch.autograd.Function):
     def forward(ctx, G: torch.Tensor, problem: Problem):
         if not torch.is_complex(G):
             raise TypeError("G must be a complex tensor of shape (K, 4, 4)")
-        Gh = G.detach().to("cpu", torch.complex128).numpy().copy()
-        cost, _ = problem.forward(Gh)
-        ctx.problem, ctx.Gh, ctx.epoch = problem, Gh, problem.epoch
+        Gd = G.detach().to(torch.device(f"cuda:{problem.device}"), torch.complex128).contiguous()
+        cost, _ = problem.forward_dev(Gd)
+        ctx.problem, ctx.Gd, ctx.epoch = problem, Gd, problem.epoch
         ctx.out_device, ctx.out_dtype = G.device, G.dtype
-        return torch.tensor(cost, dtype=torch.float64, device=G.device)
+        return cost.clone().to(G.device)
 
     @staticmethod
     def backward(ctx, grad_out):
         p = ctx.problem
         if p.epoch != ctx.epoch:
-            p.forward(ctx.Gh)                     # the checkpoints were replaced: sweep again
-        g = p.backward()
-        gt = torch.from_numpy(np.ascontiguousarray(g)).to(ctx.out_device, ctx.out_dtype)
+            p.forward_dev(ctx.Gd)                 # the checkpoints were replaced: sweep again
+        g = p.backward_dev()
+        gt = g.to(ctx.out_device, ctx.out_dtype)
         return grad_out.to(gt.real.dtype) * gt, None
 
 

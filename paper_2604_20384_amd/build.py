@@ -28,7 +28,7 @@ def build(verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src, device in (("qhvp_kernels.hip", True), ("qhvp_host.cpp", False)):
+    for src, device in (("qhvp_kernels.hip", True), ("qhvp_post.hip", True), ("qhvp_host.cpp", False)):
         obj = os.path.join(objdir, src + ".o")
         cmd = ["hipcc", f"--offload-arch={ARCH}", *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
         if device:

@@ -225,26 +225,35 @@ int lds_cycles(const int (&addr)[64], int width, bool write) {
 }
 
 // Modelled bank-conflict cycles of one complex64 backward gate step (k_bwd_out) for a gate on tile
-// bits lo, hi whose group bits 0..3 sit on tile bits p0..p3: the environment operand reads (32-bit,
-// 32 wave accesses per step; lanes over the amplitude bits lo, hi, the state arrays, real / imaginary
-// part and group bits 0, 1) and the W-tile reads and writes (64-bit, 16 each; lanes over group bits
-// 0..3 and lo, hi).  Wave-uniform parts of the addresses shift every lane alike and drop out.
-int c64_step_conflicts(int lo, int hi, int p0, int p1, int p2, int p3) {
+// bits lo, hi whose group bits 0..5 sit on tile bits p[0..6).  The environment operand reads (32-bit,
+// 32 wave accesses per step) run the lanes over the amplitude bits lo, hi, the state arrays, the
+// real / imaginary part and group bits 0, 1; the W-tile reads and writes (64-bit, 16 each) run lane l
+// over group bits 0..5 (lane l owns group l of the wave; the amplitude and the state array are
+// wave-uniform).  Wave-uniform parts of the addresses shift every lane alike and drop out.
+int c64_env_conflicts(int lo, int hi, int p0, int p1) {
   auto O = [](int b) { return lds_at(1 << b, 8); };
   auto sel = [](int v, int bit, int off) { return ((v >> bit) & 1) ? off : 0; };
-  int env[64], w[64];
+  int env[64];
   for (int l = 0; l < 64; ++l) {
     const int comp = l & 15, sub = l >> 4;
     const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
     const int tl = sel(sub, 0, O(p0)) + sel(sub, 1, O(p1)) + sel(cidx, 0, O(lo)) + sel(cidx, 1, O(hi));
     env[l] = 4 * (2 * cst * qhvp::kTspC64 + cri + 2 * tl);
-    const int col = l & 15, g = l >> 4;
-    const int tw = sel(col, 0, O(p0)) + sel(col, 1, O(p1)) + sel(col, 2, O(p2)) + sel(col, 3, O(p3)) +
-                   sel(g, 0, O(lo)) + sel(g, 1, O(hi));
-    w[l] = 8 * tw;
   }
-  return 32 * (lds_cycles(env, 4, false) - 2) + 16 * (lds_cycles(w, 8, false) - 2) +
-         16 * (lds_cycles(w, 8, true) - 4);
+  return 32 * (lds_cycles(env, 4, false) - 2);
+}
+// W-tile reads are served 32 lanes (group bits 0..4) at a time and writes 16 lanes (bits 0..3), and
+// the other lanes' addresses are the first group's shifted by a common offset, so their conflicts
+// depend only on which tile bits sit on group bits 0..4 (resp. 0..3); `bits` lists those.
+int c64_w_conflicts(const int* bits, int nbits, bool write) {
+  int w[64];
+  for (int l = 0; l < 64; ++l) {
+    int t = 0;
+    for (int i = 0; i < nbits; ++i)
+      if ((l >> i) & 1) t += lds_at(1 << bits[i], 8);
+    w[l] = 8 * t;
+  }
+  return 16 * (lds_cycles(w, 8, write) - (write ? 4 : 2));
 }
 
 // Per-pass constants of the kernels' tile addressing: the tile-enumeration mask and, per gate, the
@@ -276,24 +285,45 @@ void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
           if (b != lo && b != hi && b != f0 && b != f1) avail[k++] = b;
         for (int i = 0; i < 6; ++i) pos[i] = avail[i];
         if (elem_bytes == 8) {
-          // complex64: choose the tile bits the lanes run over (group bits 0, 1: the sub-rows of
-          // the environment operands; 0..3: the 16 columns of the gate application; the order of
-          // 2 and 3 does not matter) with the fewest modelled bank-conflict cycles per gate step
+          // complex64: choose the order of the six lane bits with the fewest modelled bank-conflict
+          // cycles per gate step: bits 0, 1 are the sub-rows of the environment operands; the W-tile
+          // reads are served 32 lanes (bits 0..4) and its writes 16 lanes (bits 0..3) at a time, so
+          // only the sets {0..4} and {0..3} matter there
+          int wr[6], ww[6][6];
+          for (int e = 0; e < 6; ++e) {   // read cost with avail[e] on group bit 5
+            int bits[5], r = 0;
+            for (int i = 0; i < 6; ++i)
+              if (i != e) bits[r++] = avail[i];
+            wr[e] = c64_w_conflicts(bits, 5, false);
+          }
+          for (int e = 0; e < 6; ++e)   // write cost with avail[e], avail[f] on group bits 4, 5
+            for (int f = e + 1; f < 6; ++f) {
+              int bits[4], r = 0;
+              for (int i = 0; i < 6; ++i)
+                if (i != e && i != f) bits[r++] = avail[i];
+              ww[e][f] = ww[f][e] = c64_w_conflicts(bits, 4, true);
+            }
           int best = -1;
           for (int a0 = 0; a0 < 6; ++a0)
-            for (int a1 = 0; a1 < 6; ++a1)
-              for (int a2 = 0; a2 < 6; ++a2)
-                for (int a3 = a2 + 1; a3 < 6; ++a3) {
-                  if (a0 == a1 || a0 == a2 || a0 == a3 || a1 == a2 || a1 == a3) continue;
-                  const int c = c64_step_conflicts(lo, hi, avail[a0], avail[a1], avail[a2], avail[a3]);
+            for (int a1 = 0; a1 < 6; ++a1) {
+              if (a1 == a0) continue;
+              const int ce = c64_env_conflicts(lo, hi, avail[a0], avail[a1]);
+              for (int e4 = 0; e4 < 6; ++e4)
+                for (int e5 = 0; e5 < 6; ++e5) {
+                  if (e4 == e5 || e4 == a0 || e4 == a1 || e5 == a0 || e5 == a1) continue;
+                  const int c = ce + wr[e5] + ww[e4][e5];
                   if (best < 0 || c < best) {
                     best = c;
-                    pos[0] = avail[a0]; pos[1] = avail[a1]; pos[2] = avail[a2]; pos[3] = avail[a3];
-                    int r = 4;
+                    pos[0] = avail[a0];
+                    pos[1] = avail[a1];
+                    int r = 2;
                     for (int i = 0; i < 6; ++i)
-                      if (i != a0 && i != a1 && i != a2 && i != a3) pos[r++] = avail[i];
+                      if (i != a0 && i != a1 && i != e4 && i != e5) pos[r++] = avail[i];
+                    pos[4] = avail[e4];
+                    pos[5] = avail[e5];
                   }
                 }
+            }
         }
         pos[6] = f0;
         pos[7] = f1;
@@ -348,6 +378,10 @@ struct Layout {
   size_t slot_bytes = 0;
   // small buffers (offsets from off_small)
   size_t o_samples, o_gates, o_dirs, o_igates, o_uref, o_tov, o_ovpart, o_envpart, o_env, o_sched;
+  // per-call FP64 buffers: the call's G and V as given (host calls stage them here), the FP64 copies
+  // the post-processing reads (G, the possibly projected V, G^-1), the gates the kept pass-boundary
+  // states belong to, the per-call flags and the outputs of host calls (cost, fidelity, grad, hvp)
+  size_t o_gin, o_vin, o_g64, o_v64, o_gi64, o_keptg, o_flags, o_out;
 };
 
 // Tile-schedule counters (one int per launch, zeroed at the start of every sweep)
@@ -385,6 +419,15 @@ bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_
   lay.o_envpart = o; o = align_up(o + (size_t)lay.n_wg_max * qhvp::kMaxGates * qhvp::kEnvVals * sizeof(double));
   lay.o_env = o;     o = align_up(o + (size_t)K * qhvp::kEnvVals * sizeof(double));
   lay.o_sched = o;   o = align_up(o + (size_t)kSchedSlots * sizeof(int));
+  const size_t g64 = (size_t)K * 32 * sizeof(double);
+  lay.o_gin = o;     o = align_up(o + g64);
+  lay.o_vin = o;     o = align_up(o + g64);
+  lay.o_g64 = o;     o = align_up(o + g64);
+  lay.o_v64 = o;     o = align_up(o + g64);
+  lay.o_gi64 = o;    o = align_up(o + g64);
+  lay.o_keptg = o;   o = align_up(o + g64);
+  lay.o_flags = o;   o = align_up(o + qhvp::kFlagCount * sizeof(int));
+  lay.o_out = o;     o = align_up(o + 2 * sizeof(double) + 2 * g64);
   lay.total = lay.off_small + o;
   return true;
 }
@@ -500,53 +543,50 @@ struct qhvp_problem {
   Layout lay;
   char* ws;
   bool owns_ws;
-  // host staging (pinned)
-  void* h_gates;   // K*16 amplitudes (device precision)
-  void* h_dirs;
-  void* h_igates;  // K*32 amplitudes: G^-1 | -G^-1 V G^-1 per gate (device precision)
-  double* h_tov;   // Ns*4
-  double* h_env;   // K*64
-  std::vector<double> last_T, last_Om;
+  // pinned host staging: the samples and U_ref gates at creation, then G | V (FP64) of host calls;
+  // the outputs of host calls (cost, fidelity, grad, hvp); the overlaps
+  void* h_in;
+  double* h_out;
+  double* h_tov;
   // two-phase evaluation: a forward sweep leaves its checkpoints for one backward sweep
-  int fwd_ready = 0, fwd_tangent = 0;
-  // backward from pass-output states (all gates well conditioned): FP64 G^-1 and V of that sweep
-  int bwd_inverse = 0;
-  std::vector<cd> bwd_Gi, bwd_V;
-  qhvp_geometry fwd_geom = QHVP_EUCLIDEAN;
-  std::vector<double> fwd_G, fwd_V;
-  // The forward states psi at the pass boundaries that stay in the workspace between calls (every
-  // boundary when there is one segment, else the segment checkpoints) belong to the gates kept_G
-  // while kept_valid: a later gradient / HVP sweep at bitwise the same G stores only tangents there.
-  int kept_valid = 0;
-  std::vector<double> kept_G;
-  hipEvent_t ev0, ev1;
-  double last_ms;
-  // optional per-launch timing: events bracket every launch of the call; stats accumulate per kind
+  int fwd_ready = 0, fwd_tangent = 0, fwd_riem = 0;
+  int last_tangent = 0, have_eval = 0;
+  // set while a gradient / HVP sweep is being enqueued: if enqueueing fails part-way, the kept
+  // pass-boundary states may be incomplete and the next sweep must not reuse them
+  int invalidate_kept = 0;
+  // device time of the last evaluation: events around its forward (0, 1) and backward (2, 3) phases
+  hipEvent_t ev[4];
+  int ev_fwd = 0, ev_bwd = 0;
+  // optional per-launch timing: events bracket every launch of the call; stats accumulate per kind.
+  // Where a device-side decision (a flag of the call) changes a launch's traffic, both figures are kept
+  // and the flag picks one when the events are collected.
   int profiling = 0;
   int sched_used = 0;   // tile-schedule counters handed out since the last reset
   std::vector<hipEvent_t> evpool;
   size_t ev_used = 0;
-  struct Pending { int kind; size_t e0; double bytes, flops; };
+  struct Pending { int kind; size_t e0; double bytes_set, bytes_clear, flops; int flag; };
   std::vector<Pending> pending;
   double k_ms[QHVP_KERNEL_KINDS] = {0}, k_bytes[QHVP_KERNEL_KINDS] = {0}, k_flops[QHVP_KERNEL_KINDS] = {0};
   long long k_count[QHVP_KERNEL_KINDS] = {0};
 
   char* phi0() { return ws + lay.off_phi0; }
   char* slot(int i) { return ws + lay.off_slots + (size_t)i * lay.slot_bytes; }
-  char* small(size_t o) { return ws + lay.off_small + o; }
+  char* small(size_t o) const { return ws + lay.off_small + o; }
   // slot indices: [0, n_ckpt) checkpoints of segments 1..J-1; [n_ckpt, n_ckpt+n_seg) in-segment
   // boundaries 1..maxlen-1; last: working / backward (a, b)
   char* ckpt(int segment) { return slot(segment - 1); }
   char* segbuf(int i) { return slot(lay.n_ckpt + i - 1); }
   char* work() { return slot(lay.n_ckpt + lay.n_seg); }
   char* second(char* slotp) { return slotp + lay.state_bytes; }
+  int* flags() const { return (int*)small(lay.o_flags); }
+  double* dbuf(size_t o) const { return (double*)small(o); }
   qhvp::Prec dprec() const { return prec == QHVP_C64_ACC64 ? qhvp::P_C64 : qhvp::P_C128; }
   size_t amp() const { return prec == QHVP_C64_ACC64 ? 8 : 16; }
 };
 
 namespace {
 
-// Per-launch timing (only when profiling is on): an event before and after the launch.
+// Per-launch timing (only when profiling is on): an event before and after the launch(es).
 hipError_t prof_begin(qhvp_problem* p) {
   if (!p->profiling) return hipSuccess;
   while (p->evpool.size() < p->ev_used + 2) {
@@ -557,20 +597,27 @@ hipError_t prof_begin(qhvp_problem* p) {
   }
   return hipEventRecord(p->evpool[p->ev_used], p->stream);
 }
-hipError_t prof_end(qhvp_problem* p, int kind, double bytes, double flops) {
+// flag < 0: the traffic is bytes_set; else bytes_set if that per-call flag is set, bytes_clear if not
+hipError_t prof_end(qhvp_problem* p, int kind, double bytes_set, double flops, int flag = -1, double bytes_clear = 0) {
   if (!p->profiling) return hipSuccess;
   hipError_t r = hipEventRecord(p->evpool[p->ev_used + 1], p->stream);
-  p->pending.push_back({kind, p->ev_used, bytes, flops});
+  p->pending.push_back({kind, p->ev_used, bytes_set, bytes_clear, flops, flag});
   p->ev_used += 2;
   return r;
 }
+// Waits for the pending launches (the last call's) and adds them to the statistics.
 hipError_t prof_collect(qhvp_problem* p) {
+  if (p->pending.empty()) return hipSuccess;
+  int fl[qhvp::kFlagCount];
+  hipError_t r = hipMemcpyAsync(fl, p->flags(), sizeof(fl), hipMemcpyDeviceToHost, p->stream);
+  if (r == hipSuccess) r = hipStreamSynchronize(p->stream);
+  if (r != hipSuccess) return r;
   for (auto& q : p->pending) {
     float ms = 0;
-    hipError_t r = hipEventElapsedTime(&ms, p->evpool[q.e0], p->evpool[q.e0 + 1]);
+    r = hipEventElapsedTime(&ms, p->evpool[q.e0], p->evpool[q.e0 + 1]);
     if (r != hipSuccess) return r;
     p->k_ms[q.kind] += ms;
-    p->k_bytes[q.kind] += q.bytes;
+    p->k_bytes[q.kind] += (q.flag < 0 || fl[q.flag] != 0) ? q.bytes_set : q.bytes_clear;
     p->k_flops[q.kind] += q.flops;
     p->k_count[q.kind] += 1;
   }
@@ -579,10 +626,6 @@ hipError_t prof_collect(qhvp_problem* p) {
   return hipSuccess;
 }
 
-// Algorithmic traffic and arithmetic of one pass (what the method must move / compute for
-// it, not counting the in-tile recomputation): S bytes per state set read or written; per gate
-// and amplitude 32 flop for psi <- G psi, 96 with the tangent; the backward adds the environment
-// products (32 flop, 96 with the tangent).
 // Tile-schedule counters: zeroed at the start of each sweep; every kernel launch takes a fresh one
 // (all in stream order, so a re-zeroing when the slots run out follows the launches that used them).
 hipError_t sched_reset(qhvp_problem* p) {
@@ -594,6 +637,10 @@ int* sched_slot(qhvp_problem* p) {
   return (int*)p->small(p->lay.o_sched) + p->sched_used++;
 }
 
+// Algorithmic traffic and arithmetic of one pass (what the method must move / compute for
+// it, not counting the in-tile recomputation): S bytes per state set read or written; per gate
+// and amplitude 32 flop for psi <- G psi, 96 with the tangent; the backward adds the environment
+// products (32 flop, 96 with the tangent).
 double state_bytes_alg(const qhvp_problem* p) { return (double)p->Ns * std::ldexp(1.0, p->n) * (double)p->amp(); }
 double pass_flops(const qhvp_problem* p, const qhvp::PassDesc& pd, int tangent, bool backward) {
   const double per = tangent ? 96.0 : 32.0;
@@ -611,14 +658,14 @@ void to_device_precision(const qhvp_problem* p, const double* src, size_t n_comp
 
 // Forward sweep of `passes` (gates at device pointer `gates`).  mode: 0 = labels (write result to
 // phi0), 1 = ansatz sweep storing checkpoints for a later backward sweep, 2 = ansatz cost only.
-// keep_psi (mode 1): the kept boundaries already hold psi for these gates; store dpsi only there.
+// Mode 1 leaves two decisions to the flags its k_prep set: psi is not stored at the boundaries that
+// stay in the workspace when they already hold it for these gates (kFlagKeep), and the final states
+// are stored (for the backward sweep from pass outputs) only if that sweep runs (kFlagInverse).
 qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& passes, const void* gates,
-                          const void* dirs, int tangent, int mode, bool keep_psi = false) {
+                          const void* dirs, int tangent, int mode) {
   const int np = (int)passes.size();
   const char* samples = p->small(p->lay.o_samples);
   double* ovpart = (double*)p->small(p->lay.o_ovpart);
-  const size_t sb = p->lay.state_bytes;
-  (void)sb;
   // segment lookup for mode 1
   std::vector<int> seg_of(np, 0);
   for (size_t j = 0; j < p->seg.size(); ++j)
@@ -659,24 +706,34 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
     }
     a.src_psi = src;
     a.src_dpsi = src ? p->second(src) : nullptr;
+    const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
+    double b_set = 0, b_clear = 0;
+    int flag = -1;
     if (mode != 0 && q == np - 1) {
       // the backward sweep from pass outputs starts from the final states (kept in the working slot)
-      a.dst_psi = (mode == 1 && p->bwd_inverse) ? p->work() : nullptr;
-      a.dst_dpsi = a.dst_psi ? p->second(p->work()) : nullptr;
+      if (mode == 1) {
+        a.dst_psi = p->work();
+        a.dst_dpsi = p->second(p->work());
+        a.store_if = p->flags() + qhvp::kFlagInverse;
+        flag = qhvp::kFlagInverse;
+      }
       a.phi0 = p->phi0();
       a.ov_part = ovpart;
+      b_clear = (src ? nst * S : 0) + S;
+      b_set = b_clear + (mode == 1 ? nst * S : 0);
     } else {
-      a.dst_psi = (keep_psi && dst_kept) ? nullptr : dst;
+      a.dst_psi = dst;
       a.dst_dpsi = p->second(dst);
+      if (mode == 1 && dst_kept) {
+        a.psi_skip = p->flags() + qhvp::kFlagKeep;
+        flag = qhvp::kFlagKeep;
+      }
+      b_clear = (src ? nst * S : 0) + (dst ? S : 0) + (tangent && dst ? S : 0);
+      b_set = flag < 0 ? b_clear : b_clear - S;   // psi not stored
     }
-    {
-      const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
-      const double bytes = (a.src_psi ? nst * S : 0) + (a.ov_part ? S : 0) + (a.dst_psi ? S : 0) +
-                           (tangent && a.dst_dpsi ? S : 0);
-      HIP_TRY(prof_begin(p));
-      LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
-      HIP_TRY(prof_end(p, QHVP_KERNEL_FORWARD, bytes, pass_flops(p, a.pd, tangent, false)));
-    }
+    HIP_TRY(prof_begin(p));
+    LAUNCH_TRY(qhvp::launch_fwd(p->dprec(), a, p->stream));
+    HIP_TRY(prof_end(p, QHVP_KERNEL_FORWARD, b_set, pass_flops(p, a.pd, tangent, false), flag, b_clear));
   }
   if (mode != 0) {
     const int tiles = 1 << (p->n - passes[np - 1].mb);
@@ -685,6 +742,9 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
   return QHVP_OK;
 }
 
+// Backward sweep of the last mode-1 forward sweep.  Each pass launches both backward kernels; the
+// call's kFlagInverse (set by k_prep) lets exactly one of them run: k_bwd_out from the pass-output
+// states, or k_bwd recomputing from the pass-input states.
 qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
   const int np = (int)p->passes.size();
   const int J = (int)p->seg.size();
@@ -693,6 +753,7 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
   const char* samples = p->small(p->lay.o_samples);
   double* envpart = (double*)p->small(p->lay.o_envpart);
   double* env = (double*)p->small(p->lay.o_env);
+  const int* finv = p->flags() + qhvp::kFlagInverse;
   char* ab = p->work();
   HIP_TRY(sched_reset(p));
   for (int j = J - 1; j >= 0; --j) {
@@ -731,11 +792,6 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       b.gates = gates;
       b.dirs = dirs;
       b.igates = p->small(p->lay.o_igates);
-      // forward states: the pass input (recomputing kernel) or the pass output (inverse kernel)
-      char* src = q == s0 ? start : p->segbuf(q - s0);
-      if (p->bwd_inverse) src = q + 1 < s1 ? p->segbuf(q + 1 - s0) : (j == J - 1 ? ab : p->ckpt(j + 1));
-      b.src_psi = src;
-      b.src_dpsi = src ? p->second(src) : nullptr;
       b.samples = samples;
       b.ab_a = ab;
       b.ab_b = p->second(ab);
@@ -744,20 +800,144 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       b.fold = (q == np - 1);
       b.store_ab = (q > 0);
       b.env_part = envpart;
+      b.run_flag = finv;
+      // forward states: the pass input (recomputing kernel) or the pass output (inverse kernel)
+      char* src_in = q == s0 ? start : p->segbuf(q - s0);
+      char* src_out = q + 1 < s1 ? p->segbuf(q + 1 - s0) : (j == J - 1 ? ab : p->ckpt(j + 1));
+      qhvp::BwdArgs bo = b, br = b;
+      bo.src_psi = src_out;
+      bo.src_dpsi = p->second(src_out);
+      bo.run_when = 1;
+      br.src_psi = src_in;
+      br.src_dpsi = src_in ? p->second(src_in) : nullptr;
+      br.run_when = 0;
       const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
-      const double bytes = (b.fold ? S : nst * S) + (src ? nst * S : 0) + (b.store_ab ? nst * S : 0);
+      const double common = (b.fold ? S : nst * S) + (b.store_ab ? nst * S : 0);
       HIP_TRY(prof_begin(p));
-      if (p->bwd_inverse) LAUNCH_TRY(qhvp::launch_bwd_out(p->dprec(), b, p->stream));
-      else LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), b, p->stream));
-      HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, bytes, pass_flops(p, b.pd, tangent, true)));
-      const int nwg = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, (long long)p->Ns << (p->n - b.pd.mb), p->bwd_inverse);
+      LAUNCH_TRY(qhvp::launch_bwd_out(p->dprec(), bo, p->stream));
+      LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), br, p->stream));
+      HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, common + nst * S, pass_flops(p, b.pd, tangent, true), qhvp::kFlagInverse,
+                       common + (src_in ? nst * S : 0)));
+      const long long items = (long long)p->Ns << (p->n - b.pd.mb);
+      const int nwg_out = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, items, 1);
+      const int nwg_rec = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, items, 0);
       HIP_TRY(prof_begin(p));
-      LAUNCH_TRY(qhvp::launch_reduce_env(envpart, nwg, b.pd, env, p->stream));
-      HIP_TRY(prof_end(p, QHVP_KERNEL_REDUCE, (double)nwg * b.pd.ng * qhvp::kEnvVals * 8, 0));
+      LAUNCH_TRY(qhvp::launch_reduce_env(envpart, nwg_out, nwg_rec, finv, b.pd, env, p->stream));
+      HIP_TRY(prof_end(p, QHVP_KERNEL_REDUCE, (double)nwg_out * b.pd.ng * qhvp::kEnvVals * 8, 0, qhvp::kFlagInverse,
+                       (double)nwg_rec * b.pd.ng * qhvp::kEnvVals * 8));
     }
   }
   return QHVP_OK;
 }
+
+// Whether ptr lies in device memory of HIP device `device` (or in managed memory).
+bool device_pointer(const void* ptr, int device) {
+  if (!ptr) return false;
+  hipPointerAttribute_t at;
+  std::memset(&at, 0, sizeof(at));
+  if (hipPointerGetAttributes(&at, ptr) != hipSuccess) {
+    (void)hipGetLastError();   // plain host memory: the query fails; leave no error behind
+    return false;
+  }
+  if (at.type == hipMemoryTypeDevice) return at.device == device;
+  return at.type == hipMemoryTypeManaged;
+}
+
+bool env_recompute() {
+  const char* choice = std::getenv("QHVP_BACKWARD");
+  return choice && std::strcmp(choice, "recompute") == 0;
+}
+
+// Forward phase of one evaluation on device inputs d_G, d_V (K*16 complex FP64 each; d_V only for
+// mode 2).  mode 0: cost sweep (nothing kept); 1: gradient sweep; 2: HVP sweep (tangent states).
+// Enqueues k_prep and the sweep on the problem's stream; returns without waiting.
+qhvp_status core_forward(qhvp_problem* p, const double* d_G, const double* d_V, int riem, int mode) {
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  HIP_TRY(prof_collect(p));
+  p->fwd_ready = 0;
+  p->ev_fwd = p->ev_bwd = 0;
+  const int tangent = mode == 2 ? 1 : 0;
+  HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+  qhvp::PrepArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.K = p->K;
+  pa.prec = p->dprec();
+  pa.tangent = tangent;
+  pa.riem = mode != 0 ? riem : 0;
+  pa.with_inverse = (mode != 0 && !env_recompute()) ? 1 : 0;
+  pa.keep_mode = mode != 0 ? 1 : 0;
+  pa.invalidate_kept = p->invalidate_kept;
+  pa.G_in = d_G;
+  pa.V_in = tangent ? d_V : nullptr;
+  pa.gates = p->small(p->lay.o_gates);
+  pa.dirs = p->small(p->lay.o_dirs);
+  pa.igates = p->small(p->lay.o_igates);
+  pa.g64 = p->dbuf(p->lay.o_g64);
+  pa.v64 = p->dbuf(p->lay.o_v64);
+  pa.gi64 = p->dbuf(p->lay.o_gi64);
+  pa.kept_g = p->dbuf(p->lay.o_keptg);
+  pa.flags = p->flags();
+  if (mode != 0) p->invalidate_kept = 1;   // cleared once the whole sweep is enqueued
+  LAUNCH_TRY(qhvp::launch_prep(pa, p->stream));
+  qhvp_status st = forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent,
+                                 mode == 0 ? 2 : 1);
+  if (st) return st;
+  if (mode != 0) p->invalidate_kept = 0;
+  HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+  p->ev_fwd = 1;
+  p->have_eval = 1;
+  p->last_tangent = tangent;
+  if (mode != 0) {
+    p->fwd_ready = 1;
+    p->fwd_tangent = tangent;
+    p->fwd_riem = riem;
+  }
+  return QHVP_OK;
+}
+
+// Post-processing on the device (k_post): outputs are device pointers (null: not written).
+qhvp_status core_post(qhvp_problem* p, int mode, int tangent, int riem, double* cost, double* fidelity, double* grad,
+                      double* hvp) {
+  qhvp::PostArgs pa;
+  std::memset(&pa, 0, sizeof(pa));
+  pa.K = p->K;
+  pa.Ns = p->Ns;
+  pa.tangent = tangent;
+  pa.riem = riem;
+  pa.mode = mode;
+  pa.tov = (const double*)p->small(p->lay.o_tov);
+  pa.env = (const double*)p->small(p->lay.o_env);
+  pa.flags = p->flags();
+  pa.g64 = p->dbuf(p->lay.o_g64);
+  pa.v64 = p->dbuf(p->lay.o_v64);
+  pa.gi64 = p->dbuf(p->lay.o_gi64);
+  pa.cost = cost;
+  pa.fidelity = fidelity;
+  pa.grad = grad;
+  pa.hvp = hvp;
+  LAUNCH_TRY(qhvp::launch_post(pa, p->stream));
+  return QHVP_OK;
+}
+
+// Backward phase of the last gradient / HVP forward phase (its checkpoints are consumed), then the
+// post-processing into the device outputs (cost and fidelity too when given).
+qhvp_status core_backward(qhvp_problem* p, double* cost, double* fidelity, double* grad, double* hvp) {
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  if (!p->fwd_ready) return fail(QHVP_ERR_INVALID, "no forward sweep to differentiate (call qhvp_forward first)");
+  p->fwd_ready = 0;
+  HIP_TRY(hipEventRecord(p->ev[2], p->stream));
+  qhvp_status st = backward_sweep(p, p->fwd_tangent);
+  if (st) return st;
+  const int mode = qhvp::kPostDeriv | ((cost || fidelity) ? qhvp::kPostCost : 0);
+  st = core_post(p, mode, p->fwd_tangent, p->fwd_riem, cost, fidelity, grad, hvp);
+  if (st) return st;
+  HIP_TRY(hipEventRecord(p->ev[3], p->stream));
+  p->ev_bwd = 1;
+  return QHVP_OK;
+}
+
+// ---- host calls: validated on the host, staged to the device, evaluated by the device path, and
+// the outputs copied back once everything succeeded (outputs are untouched on every error path)
 
 qhvp_status check_gates(const qhvp_problem* p, const double* G, const char* what) {
   if (!G) return fail(QHVP_ERR_INVALID, std::string(what) + " is NULL");
@@ -765,168 +945,67 @@ qhvp_status check_gates(const qhvp_problem* p, const double* G, const char* what
   return QHVP_OK;
 }
 
-qhvp_status finish_call(qhvp_problem* p, int copy_env, int tangent) {
-  if (copy_env)
-    HIP_TRY(hipMemcpyAsync(p->h_env, p->small(p->lay.o_env), (size_t)p->K * qhvp::kEnvVals * sizeof(double),
-                           hipMemcpyDeviceToHost, p->stream));
-  HIP_TRY(hipEventRecord(p->ev1, p->stream));
-  HIP_TRY(hipStreamSynchronize(p->stream));
-  float ms = 0;
-  HIP_TRY(hipEventElapsedTime(&ms, p->ev0, p->ev1));
-  p->last_ms += ms;
-  HIP_TRY(prof_collect(p));
-  (void)tangent;
+qhvp_status check_host_call(const qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom) {
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  qhvp_status st = check_gates(p, G, "G");
+  if (st) return st;
+  if (V) {
+    if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
+    st = check_gates(p, V, "V");
+    if (st) return st;
+  }
+  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->K, G) > 1e-10)
+    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
   return QHVP_OK;
 }
 
-// The backward sweep may start each pass from its OUTPUT forward states and undo the gates on them
-// (k_bwd_out) when every gate is well conditioned: then the inverse gates G^-1 and Y = -G^-1 V G^-1
-// (FP64 here, device precision on the device) are staged.  Condition: |G|_F |G^-1|_F <= 8 (4 for a
-// unitary gate), so that undoing the at most kMaxGates gates of a pass loses at most a few bits.
-void prepare_inverse(qhvp_problem* p, const double* G, const double* V) {
-  p->bwd_inverse = 0;
-  const char* choice = std::getenv("QHVP_BACKWARD");
-  if (choice && std::strcmp(choice, "recompute") == 0) return;
-  p->bwd_Gi.assign((size_t)p->K * 16, cd(0));
-  p->bwd_V.assign((size_t)p->K * 16, cd(0));
-  std::vector<double> stage((size_t)p->K * 64);
-  for (int k = 0; k < p->K; ++k) {
-    M4 g, gi, v, t, y;
-    load4(G + (size_t)k * 32, g);
-    if (!inv4(g, gi) || fro4(g) * fro4(gi) > 8.0) return;
-    if (V) load4(V + (size_t)k * 32, v);
-    else for (int i = 0; i < 16; ++i) v[i] = 0;
-    mul4(gi, v, t);
-    mul4(t, gi, y);
-    for (int i = 0; i < 16; ++i) {
-      p->bwd_Gi[(size_t)k * 16 + i] = gi[i];
-      p->bwd_V[(size_t)k * 16 + i] = v[i];
-      stage[(size_t)k * 64 + 2 * i] = gi[i].real();
-      stage[(size_t)k * 64 + 2 * i + 1] = gi[i].imag();
-      stage[(size_t)k * 64 + 32 + 2 * i] = -y[i].real();
-      stage[(size_t)k * 64 + 32 + 2 * i + 1] = -y[i].imag();
-    }
-  }
-  to_device_precision(p, stage.data(), (size_t)p->K * 32, p->h_igates);
-  p->bwd_inverse = 1;
-}
-
-// Output-side environment sums of the inverse backward sweep -> input-side ones, per gate (FP64):
-// E = Et G^-T, D = (Dt - E V^T) G^-T, in place in h_env (E at [0, 32), D at [32, 64), entry 4x+y).
-void map_output_envs(qhvp_problem* p, int tangent) {
-  for (int k = 0; k < p->K; ++k) {
-    double* e = p->h_env + (size_t)k * 64;
-    const cd* gi = &p->bwd_Gi[(size_t)k * 16];
-    const cd* v = &p->bwd_V[(size_t)k * 16];
-    cd Et[16], Dt[16], E[16], W[16];
-    for (int i = 0; i < 16; ++i) { Et[i] = cd(e[2 * i], e[2 * i + 1]); Dt[i] = cd(e[32 + 2 * i], e[32 + 2 * i + 1]); }
-    for (int x = 0; x < 4; ++x)
-      for (int y = 0; y < 4; ++y) {
-        cd sE = 0;
-        for (int z = 0; z < 4; ++z) sE += Et[4 * x + z] * gi[4 * y + z];
-        E[4 * x + y] = sE;
-      }
-    for (int x = 0; x < 4; ++x)   // W = Dt - E V^T
-      for (int z = 0; z < 4; ++z) {
-        cd w = Dt[4 * x + z];
-        if (tangent)
-          for (int u = 0; u < 4; ++u) w -= E[4 * x + u] * v[4 * z + u];
-        W[4 * x + z] = w;
-      }
-    for (int x = 0; x < 4; ++x)
-      for (int y = 0; y < 4; ++y) {
-        cd sD = 0;
-        for (int z = 0; z < 4; ++z) sD += W[4 * x + z] * gi[4 * y + z];
-        e[2 * (4 * x + y)] = E[4 * x + y].real();
-        e[2 * (4 * x + y) + 1] = E[4 * x + y].imag();
-        e[32 + 2 * (4 * x + y)] = sD.real();
-        e[32 + 2 * (4 * x + y) + 1] = sD.imag();
-      }
-  }
-}
-
-// Forward phase.  mode 0: cost only (no checkpoints kept); 1: gradient sweep; 2: HVP sweep.  Uploads
-// G (and V), sweeps, and brings the per-sample overlaps T_s (and Omega_s) back to the host.
-qhvp_status phase_forward(qhvp_problem* p, const double* G, const double* V, int mode) {
+// Copies host G (and V) into the workspace's input buffers through pinned staging.
+qhvp_status stage_inputs(qhvp_problem* p, const double* G, const double* V) {
   HIP_TRY(hipSetDevice(p->ctx->device));
-  p->fwd_ready = 0;
-  p->last_ms = 0;
+  const size_t gb = (size_t)p->K * 32 * sizeof(double);
+  std::memcpy(p->h_in, G, gb);
+  HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_gin), p->h_in, gb, hipMemcpyHostToDevice, p->stream));
+  if (V) {
+    std::memcpy((char*)p->h_in + gb, V, gb);
+    HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_vin), (char*)p->h_in + gb, gb, hipMemcpyHostToDevice, p->stream));
+  }
+  return QHVP_OK;
+}
+
+// Device output staging of host calls: cost, fidelity, grad (K*32), hvp (K*32) doubles.
+double* out_cost(qhvp_problem* p) { return p->dbuf(p->lay.o_out); }
+double* out_grad(qhvp_problem* p) { return p->dbuf(p->lay.o_out) + 2; }
+double* out_hvp(qhvp_problem* p) { return p->dbuf(p->lay.o_out) + 2 + (size_t)p->K * 32; }
+
+// Brings the staged outputs back, waits, and (only then) writes the caller's outputs.
+qhvp_status finish_host_call(qhvp_problem* p, double* cost, double* fidelity, double* grad, double* hvp) {
   const size_t gn = (size_t)p->K * 32;
-  const bool keep = mode != 0 && p->kept_valid && p->kept_G.size() == gn &&
-                    std::memcmp(p->kept_G.data(), G, gn * sizeof(double)) == 0;
-  if (mode != 0 && !keep) p->kept_valid = 0;   // this sweep overwrites the kept boundaries
-  to_device_precision(p, G, (size_t)p->K * 16, p->h_gates);
-  HIP_TRY(hipEventRecord(p->ev0, p->stream));
-  HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_gates), p->h_gates, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
-  if (mode == 2) {
-    to_device_precision(p, V, (size_t)p->K * 16, p->h_dirs);
-    HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_dirs), p->h_dirs, (size_t)p->K * 16 * p->amp(), hipMemcpyHostToDevice, p->stream));
-  }
-  const int tangent = mode == 2 ? 1 : 0;
-  if (mode != 0) {
-    prepare_inverse(p, G, tangent ? V : nullptr);
-    if (p->bwd_inverse)
-      HIP_TRY(hipMemcpyAsync(p->small(p->lay.o_igates), p->h_igates, (size_t)p->K * 32 * p->amp(), hipMemcpyHostToDevice,
-                             p->stream));
-  }
-  qhvp_status st = mode == 0 ? forward_sweep(p, p->passes, p->small(p->lay.o_gates), nullptr, 0, 2)
-                             : forward_sweep(p, p->passes, p->small(p->lay.o_gates), p->small(p->lay.o_dirs), tangent, 1,
-                                             keep);
-  if (st) return st;
-  HIP_TRY(hipMemcpyAsync(p->h_tov, p->small(p->lay.o_tov), (size_t)p->Ns * 4 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
-  st = finish_call(p, 0, tangent);
-  if (st) return st;
-  p->last_T.assign(2 * p->Ns, 0.0);
-  p->last_Om.assign(2 * p->Ns, 0.0);
-  for (int s = 0; s < p->Ns; ++s) {
-    p->last_T[2 * s] = p->h_tov[4 * s];
-    p->last_T[2 * s + 1] = p->h_tov[4 * s + 1];
-    if (tangent) {
-      p->last_Om[2 * s] = p->h_tov[4 * s + 2];
-      p->last_Om[2 * s + 1] = p->h_tov[4 * s + 3];
-    }
-  }
-  if (mode != 0) {
-    p->fwd_ready = 1;
-    p->fwd_tangent = tangent;
-    if (!keep) p->kept_G.assign(G, G + gn);
-    p->kept_valid = 1;
-  }
+  const size_t cnt = 2 + ((grad || hvp) ? (hvp ? 2 * gn : gn) : 0);
+  HIP_TRY(hipMemcpyAsync(p->h_out, out_cost(p), cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  int status = 0;
+  HIP_TRY(hipMemcpyAsync(p->h_tov, p->flags() + qhvp::kFlagStatus, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  std::memcpy(&status, p->h_tov, sizeof(int));
+  if (status != 0) return fail(QHVP_ERR_INVALID, "the device rejected the inputs (status " + std::to_string(status) + ")");
+  if (cost) *cost = p->h_out[0];
+  if (fidelity) *fidelity = p->h_out[1];
+  if (grad) std::memcpy(grad, p->h_out + 2, gn * sizeof(double));
+  if (hvp) std::memcpy(hvp, p->h_out + 2 + gn, gn * sizeof(double));
   return QHVP_OK;
 }
 
-// Backward phase of the last gradient / HVP forward phase (its checkpoints are consumed).
-qhvp_status phase_backward(qhvp_problem* p) {
-  HIP_TRY(hipSetDevice(p->ctx->device));
-  if (!p->fwd_ready) return fail(QHVP_ERR_INVALID, "no forward sweep to differentiate (call qhvp_forward first)");
-  p->fwd_ready = 0;
-  HIP_TRY(hipEventRecord(p->ev0, p->stream));
-  qhvp_status st = backward_sweep(p, p->fwd_tangent);
+qhvp_status host_forward(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
+                         double* fidelity) {
+  qhvp_status st = check_host_call(p, G, V, geom);
   if (st) return st;
-  st = finish_call(p, 1, p->fwd_tangent);
+  st = stage_inputs(p, G, V);
   if (st) return st;
-  if (p->bwd_inverse) map_output_envs(p, p->fwd_tangent);
-  return QHVP_OK;
-}
-
-// Alg. 2 post-processing over samples: F = mean |T_s|^2; with the folded environments
-// Ehat_k = sum_s conj(T_s) dT_s/dG_k and Dhat_k = sum_s conj(Omega_s) dT_s/dG_k + conj(T_s) D(dT_s/dG_k)[V],
-// grad C = -(2/N_s) conj(Ehat) and H(C)[V] = -(2/N_s) conj(Dhat) (cost 1 - F differentiated).
-double fidelity_of(const qhvp_problem* p) {
-  double F = 0;
-  for (int s = 0; s < p->Ns; ++s) F += p->h_tov[4 * s] * p->h_tov[4 * s] + p->h_tov[4 * s + 1] * p->h_tov[4 * s + 1];
-  return F / p->Ns;
-}
-
-void env_to_output(const qhvp_problem* p, int which, double* out) {
-  const double f = -2.0 / p->Ns;
-  for (int k = 0; k < p->K; ++k)
-    for (int e = 0; e < 16; ++e) {
-      const double re = p->h_env[(size_t)k * 64 + which * 32 + 2 * e];
-      const double im = p->h_env[(size_t)k * 64 + which * 32 + 2 * e + 1];
-      out[(size_t)k * 32 + 2 * e] = f * re;
-      out[(size_t)k * 32 + 2 * e + 1] = -f * im;
-    }
+  const double* dv = V ? p->dbuf(p->lay.o_vin) : nullptr;
+  st = core_forward(p, p->dbuf(p->lay.o_gin), dv, geom == QHVP_RIEMANNIAN, V ? 2 : 1);
+  if (st) return st;
+  st = core_post(p, qhvp::kPostCost, 0, 0, out_cost(p), out_cost(p) + 1, nullptr, nullptr);
+  if (st) return st;
+  return finish_host_call(p, cost, fidelity, nullptr, nullptr);
 }
 
 }  // namespace
@@ -934,7 +1013,7 @@ void env_to_output(const qhvp_problem* p, int which, double* out) {
 // --------------------------------------------------------------------------------------------
 extern "C" {
 
-int qhvp_version(void) { return 100; }
+int qhvp_version(void) { return 200; }
 
 const char* qhvp_last_error(void) { return g_err.c_str(); }
 
@@ -1014,10 +1093,9 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
   fill_tile_offsets(p->ref_passes, (int)p->amp());
   p->seg = plan_segments(n, L, ckpt_every);
   p->lay = lay;
-  p->last_ms = 0;
-  p->h_gates = p->h_dirs = p->h_igates = nullptr;
-  p->h_tov = p->h_env = nullptr;
-  p->ev0 = p->ev1 = nullptr;
+  p->h_in = nullptr;
+  p->h_out = p->h_tov = nullptr;
+  for (auto& e : p->ev) e = nullptr;
   auto cleanup_fail = [&](qhvp_status st, const std::string& msg) {
     qhvp_problem_destroy(p);
     return fail(st, msg);
@@ -1032,22 +1110,24 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
     if (e != hipSuccess) { p->ws = nullptr; return cleanup_fail(QHVP_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)); }
   }
   const size_t amp = p->amp();
-  const size_t stage = std::max((size_t)std::max(p->K, Kr) * 16, (size_t)n_samples * n * 2) * amp;
-  if (hipHostMalloc(&p->h_gates, stage) != hipSuccess || hipHostMalloc(&p->h_dirs, stage) != hipSuccess ||
-      hipHostMalloc(&p->h_igates, (size_t)p->K * 32 * amp) != hipSuccess ||
-      hipHostMalloc((void**)&p->h_tov, (size_t)n_samples * 4 * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&p->h_env, (size_t)p->K * qhvp::kEnvVals * sizeof(double)) != hipSuccess)
+  const size_t in_bytes = std::max({(size_t)p->K * 64 * sizeof(double), (size_t)Kr * 16 * amp, (size_t)n_samples * n * 2 * amp});
+  if (hipHostMalloc(&p->h_in, in_bytes) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_out, (2 + (size_t)p->K * 64) * sizeof(double)) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_tov, std::max((size_t)n_samples * 4, (size_t)qhvp::kFlagCount) * sizeof(double)) != hipSuccess)
     return cleanup_fail(QHVP_ERR_NOMEM, "pinned host allocation failed");
-  if (hipEventCreate(&p->ev0) != hipSuccess || hipEventCreate(&p->ev1) != hipSuccess)
-    return cleanup_fail(QHVP_ERR_DEVICE, "hipEventCreate failed");
+  for (auto& e : p->ev)
+    if (hipEventCreate(&e) != hipSuccess) return cleanup_fail(QHVP_ERR_DEVICE, "hipEventCreate failed");
 
-  // samples and U_ref gates to the device, then labels phi0 = U_ref psi (a forward sweep of U_ref)
-  to_device_precision(p, samples, (size_t)n_samples * n * 2, p->h_gates);
-  if (hipMemcpyAsync(p->small(lay.o_samples), p->h_gates, (size_t)n_samples * n * 2 * amp, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
+  // per-call flags start cleared (no kept states); samples and U_ref gates to the device, then the
+  // labels phi0 = U_ref psi (a forward sweep of U_ref)
+  if (qhvp::launch_zero_ints(p->flags(), qhvp::kFlagCount, p->stream) != 0)
+    return cleanup_fail(QHVP_ERR_DEVICE, "clearing the call flags failed");
+  to_device_precision(p, samples, (size_t)n_samples * n * 2, p->h_in);
+  if (hipMemcpyAsync(p->small(lay.o_samples), p->h_in, (size_t)n_samples * n * 2 * amp, hipMemcpyHostToDevice, p->stream) != hipSuccess ||
       hipStreamSynchronize(p->stream) != hipSuccess)
     return cleanup_fail(QHVP_ERR_DEVICE, "copy of samples failed");
-  to_device_precision(p, uref_gates, (size_t)Kr * 16, p->h_gates);
-  if (hipMemcpyAsync(p->small(lay.o_uref), p->h_gates, (size_t)Kr * 16 * amp, hipMemcpyHostToDevice, p->stream) != hipSuccess)
+  to_device_precision(p, uref_gates, (size_t)Kr * 16, p->h_in);
+  if (hipMemcpyAsync(p->small(lay.o_uref), p->h_in, (size_t)Kr * 16 * amp, hipMemcpyHostToDevice, p->stream) != hipSuccess)
     return cleanup_fail(QHVP_ERR_DEVICE, "copy of U_ref failed");
   qhvp_status st = forward_sweep(p, p->ref_passes, p->small(lay.o_uref), nullptr, 0, 0);
   if (st != QHVP_OK) { std::string m = g_err; qhvp_problem_destroy(p); return fail(st, m); }
@@ -1061,13 +1141,11 @@ void qhvp_problem_destroy(qhvp_problem* p) {
   if (p->stream) hipStreamSynchronize(p->stream);
   else hipDeviceSynchronize();
   if (p->owns_ws && p->ws) hipFree(p->ws);
-  if (p->h_gates) hipHostFree(p->h_gates);
-  if (p->h_dirs) hipHostFree(p->h_dirs);
-  if (p->h_igates) hipHostFree(p->h_igates);
+  if (p->h_in) hipHostFree(p->h_in);
+  if (p->h_out) hipHostFree(p->h_out);
   if (p->h_tov) hipHostFree(p->h_tov);
-  if (p->h_env) hipHostFree(p->h_env);
-  if (p->ev0) hipEventDestroy(p->ev0);
-  if (p->ev1) hipEventDestroy(p->ev1);
+  for (auto e : p->ev)
+    if (e) hipEventDestroy(e);
   for (auto e : p->evpool) hipEventDestroy(e);
   delete p;
 }
@@ -1076,64 +1154,28 @@ qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fi
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
   qhvp_status st = check_gates(p, G, "G");
   if (st) return st;
-  st = phase_forward(p, G, nullptr, 0);
+  st = stage_inputs(p, G, nullptr);
   if (st) return st;
-  const double F = fidelity_of(p);
-  if (cost) *cost = 1.0 - F;
-  if (fidelity) *fidelity = F;
-  return QHVP_OK;
+  st = core_forward(p, p->dbuf(p->lay.o_gin), nullptr, 0, 0);
+  if (st) return st;
+  st = core_post(p, qhvp::kPostCost, 0, 0, out_cost(p), out_cost(p) + 1, nullptr, nullptr);
+  if (st) return st;
+  return finish_host_call(p, cost, fidelity, nullptr, nullptr);
 }
 
 qhvp_status qhvp_forward(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
                          double* fidelity) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
-  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
-  qhvp_status st = check_gates(p, G, "G");
-  if (st) return st;
-  if (V) {
-    if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
-    st = check_gates(p, V, "V");
-    if (st) return st;
-  }
-  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->K, G) > 1e-10)
-    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
-  p->fwd_G.assign(G, G + (size_t)p->K * 32);
-  p->fwd_V.clear();
-  if (V) {
-    p->fwd_V.assign(V, V + (size_t)p->K * 32);
-    // the Riemannian HVP formula assumes a tangent direction: project V first
-    if (geom == QHVP_RIEMANNIAN) qhvp_project(p->K, G, V, p->fwd_V.data());
-  }
-  p->fwd_geom = geom;
-  st = phase_forward(p, G, V ? p->fwd_V.data() : nullptr, V ? 2 : 1);
-  if (st) return st;
-  const double F = fidelity_of(p);
-  if (cost) *cost = 1.0 - F;
-  if (fidelity) *fidelity = F;
-  return QHVP_OK;
+  return host_forward(p, G, V, geom, cost, fidelity);
 }
 
 qhvp_status qhvp_backward(qhvp_problem* p, double* grad, double* hvp) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
   if (!p->fwd_ready) return fail(QHVP_ERR_INVALID, "no forward sweep to differentiate (call qhvp_forward first)");
   if (hvp && !p->fwd_tangent) return fail(QHVP_ERR_INVALID, "the last forward sweep had no direction V");
-  const int tangent = p->fwd_tangent;
-  qhvp_status st = phase_backward(p);
+  qhvp_status st = core_backward(p, nullptr, nullptr, grad ? out_grad(p) : nullptr, hvp ? out_hvp(p) : nullptr);
   if (st) return st;
-  std::vector<double> g((size_t)p->K * 32), h;
-  env_to_output(p, 0, g.data());
-  if (tangent) {
-    h.resize((size_t)p->K * 32);
-    env_to_output(p, 1, h.data());
-  }
-  if (p->fwd_geom == QHVP_RIEMANNIAN) {
-    if (grad) qhvp_project(p->K, p->fwd_G.data(), g.data(), grad);
-    if (hvp) return qhvp_riemannian_hvp(p->K, p->fwd_G.data(), g.data(), h.data(), p->fwd_V.data(), hvp);
-    return QHVP_OK;
-  }
-  if (grad) std::memcpy(grad, g.data(), g.size() * sizeof(double));
-  if (hvp) std::memcpy(hvp, h.data(), h.size() * sizeof(double));
-  return QHVP_OK;
+  return finish_host_call(p, nullptr, nullptr, grad, hvp);
 }
 
 qhvp_status qhvp_hvp_batch(qhvp_problem* p, const double* G, int n_dirs, const double* V, qhvp_geometry geom,
@@ -1142,13 +1184,10 @@ qhvp_status qhvp_hvp_batch(qhvp_problem* p, const double* G, int n_dirs, const d
   if (n_dirs < 1) return fail(QHVP_ERR_INVALID, "n_dirs must be positive");
   if (!V || !hvp) return fail(QHVP_ERR_INVALID, "V and hvp must not be NULL");
   if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
-  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
-  qhvp_status st = check_gates(p, G, "G");
+  qhvp_status st = check_host_call(p, G, nullptr, geom);
   if (st) return st;
   const size_t gn = (size_t)p->K * 32;
   if (!finite_all(V, gn * (size_t)n_dirs)) return fail(QHVP_ERR_INVALID, "V has non-finite entries");
-  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->K, G) > 1e-10)
-    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
   // the first direction stores psi at the kept boundaries (unless they already belong to G); the
   // others read it there
   std::vector<double> out(gn * (size_t)n_dirs), g(gn);
@@ -1168,26 +1207,128 @@ qhvp_status qhvp_hvp_batch(qhvp_problem* p, const double* G, int n_dirs, const d
 int qhvp_states_kept_for(const qhvp_problem* p, const double* G) {
   if (!p || !G) return -1;
   const size_t gn = (size_t)p->K * 32;
-  return p->kept_valid && p->kept_G.size() == gn && std::memcmp(p->kept_G.data(), G, gn * sizeof(double)) == 0;
+  int fl[qhvp::kFlagCount];
+  std::vector<double> kg(gn);
+  if (hipSetDevice(p->ctx->device) != hipSuccess ||
+      hipMemcpyAsync(fl, p->flags(), sizeof(fl), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+      hipMemcpyAsync(kg.data(), p->small(p->lay.o_keptg), gn * sizeof(double), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess)
+    return -1;
+  return (!p->invalidate_kept && fl[qhvp::kFlagKeptValid] && std::memcmp(kg.data(), G, gn * sizeof(double)) == 0) ? 1 : 0;
 }
 
-qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom, double* cost, double* grad) {
+qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom, double* cost, double* fidelity,
+                      double* grad) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
   if (!grad) return fail(QHVP_ERR_INVALID, "grad is NULL");
-  qhvp_status st = qhvp_forward(p, G, nullptr, geom, cost, nullptr);
+  qhvp_status st = check_host_call(p, G, nullptr, geom);
   if (st) return st;
-  return qhvp_backward(p, grad, nullptr);
+  st = stage_inputs(p, G, nullptr);
+  if (st) return st;
+  st = core_forward(p, p->dbuf(p->lay.o_gin), nullptr, geom == QHVP_RIEMANNIAN, 1);
+  if (st) return st;
+  st = core_backward(p, out_cost(p), out_cost(p) + 1, out_grad(p), nullptr);
+  if (st) return st;
+  return finish_host_call(p, cost, fidelity, grad, nullptr);
 }
 
 qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
-                     double* grad, double* hvp) {
+                     double* fidelity, double* grad, double* hvp) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
   if (!hvp) return fail(QHVP_ERR_INVALID, "hvp is NULL");
   if (!V) return fail(QHVP_ERR_INVALID, "V is NULL");
-  qhvp_status st = qhvp_forward(p, G, V, geom, cost, nullptr);
+  qhvp_status st = check_host_call(p, G, V, geom);
   if (st) return st;
-  return qhvp_backward(p, grad, hvp);
+  st = stage_inputs(p, G, V);
+  if (st) return st;
+  st = core_forward(p, p->dbuf(p->lay.o_gin), p->dbuf(p->lay.o_vin), geom == QHVP_RIEMANNIAN, 2);
+  if (st) return st;
+  st = core_backward(p, out_cost(p), out_cost(p) + 1, out_grad(p), out_hvp(p));
+  if (st) return st;
+  return finish_host_call(p, cost, fidelity, grad, hvp);
 }
+
+// ---- device-pointer calls: inputs and outputs in device memory, enqueued on the problem's stream
+
+namespace {
+qhvp_status check_dev_call(const qhvp_problem* p, const double* d_G, const double* d_V, qhvp_geometry geom,
+                           std::initializer_list<const double*> outs) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  const int dev = p->ctx->device;
+  if (!device_pointer(d_G, dev)) return fail(QHVP_ERR_INVALID, "G is not device memory of the problem's device");
+  if (d_V) {
+    if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
+    if (!device_pointer(d_V, dev)) return fail(QHVP_ERR_INVALID, "V is not device memory of the problem's device");
+  }
+  for (const double* o : outs)
+    if (o && !device_pointer(o, dev)) return fail(QHVP_ERR_INVALID, "an output is not device memory of the problem's device");
+  return QHVP_OK;
+}
+}  // namespace
+
+qhvp_status qhvp_cost_dev(qhvp_problem* p, const double* d_G, double* d_cost, double* d_fidelity) {
+  qhvp_status st = check_dev_call(p, d_G, nullptr, QHVP_EUCLIDEAN, {d_cost, d_fidelity});
+  if (st) return st;
+  st = core_forward(p, d_G, nullptr, 0, 0);
+  if (st) return st;
+  return core_post(p, qhvp::kPostCost, 0, 0, d_cost, d_fidelity, nullptr, nullptr);
+}
+
+qhvp_status qhvp_forward_dev(qhvp_problem* p, const double* d_G, const double* d_V, qhvp_geometry geom, double* d_cost,
+                             double* d_fidelity) {
+  qhvp_status st = check_dev_call(p, d_G, d_V, geom, {d_cost, d_fidelity});
+  if (st) return st;
+  st = core_forward(p, d_G, d_V, geom == QHVP_RIEMANNIAN, d_V ? 2 : 1);
+  if (st) return st;
+  if (!d_cost && !d_fidelity) return QHVP_OK;
+  return core_post(p, qhvp::kPostCost, 0, 0, d_cost, d_fidelity, nullptr, nullptr);
+}
+
+qhvp_status qhvp_backward_dev(qhvp_problem* p, double* d_grad, double* d_hvp) {
+  if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  if (!p->fwd_ready) return fail(QHVP_ERR_INVALID, "no forward sweep to differentiate (call qhvp_forward_dev first)");
+  if (d_hvp && !p->fwd_tangent) return fail(QHVP_ERR_INVALID, "the last forward sweep had no direction V");
+  const int dev = p->ctx->device;
+  if ((d_grad && !device_pointer(d_grad, dev)) || (d_hvp && !device_pointer(d_hvp, dev)))
+    return fail(QHVP_ERR_INVALID, "an output is not device memory of the problem's device");
+  return core_backward(p, nullptr, nullptr, d_grad, d_hvp);
+}
+
+qhvp_status qhvp_grad_dev(qhvp_problem* p, const double* d_G, qhvp_geometry geom, double* d_cost, double* d_fidelity,
+                          double* d_grad) {
+  if (!d_grad) return fail(QHVP_ERR_INVALID, "grad is NULL");
+  qhvp_status st = check_dev_call(p, d_G, nullptr, geom, {d_cost, d_fidelity, d_grad});
+  if (st) return st;
+  st = core_forward(p, d_G, nullptr, geom == QHVP_RIEMANNIAN, 1);
+  if (st) return st;
+  return core_backward(p, d_cost, d_fidelity, d_grad, nullptr);
+}
+
+qhvp_status qhvp_hvp_dev(qhvp_problem* p, const double* d_G, const double* d_V, qhvp_geometry geom, double* d_cost,
+                         double* d_fidelity, double* d_grad, double* d_hvp) {
+  if (!d_hvp || !d_V) return fail(QHVP_ERR_INVALID, "V and hvp must not be NULL");
+  qhvp_status st = check_dev_call(p, d_G, d_V, geom, {d_cost, d_fidelity, d_grad, d_hvp});
+  if (st) return st;
+  st = core_forward(p, d_G, d_V, geom == QHVP_RIEMANNIAN, 2);
+  if (st) return st;
+  return core_backward(p, d_cost, d_fidelity, d_grad, d_hvp);
+}
+
+qhvp_status qhvp_device_status(qhvp_problem* p, int* status) {
+  if (!p || !status) return fail(QHVP_ERR_INVALID, "bad arguments");
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  int v = 0;
+  HIP_TRY(hipMemcpyAsync(p->h_tov, p->flags() + qhvp::kFlagStatus, sizeof(int), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  std::memcpy(&v, p->h_tov, sizeof(int));
+  *status = v;
+  return QHVP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 // ---- translationally invariant circuits (App. E): one gate G_(l) per layer ----------------------
 
@@ -1221,7 +1362,7 @@ qhvp_status qhvp_grad_ti(qhvp_problem* p, const double* G_layers, qhvp_geometry 
     return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
   std::vector<double> G, g((size_t)p->K * 32), gl((size_t)p->L * 32);
   ti_expand(p, G_layers, G);
-  qhvp_status st = qhvp_grad(p, G.data(), QHVP_EUCLIDEAN, cost, g.data());
+  qhvp_status st = qhvp_grad(p, G.data(), QHVP_EUCLIDEAN, cost, nullptr, g.data());
   if (st) return st;
   ti_reduce(p, g.data(), gl.data());
   if (geom == QHVP_RIEMANNIAN) return qhvp_project(p->L, G_layers, gl.data(), grad_layers);
@@ -1243,7 +1384,7 @@ qhvp_status qhvp_hvp_ti(qhvp_problem* p, const double* G_layers, const double* V
   std::vector<double> G, V, g((size_t)p->K * 32), h((size_t)p->K * 32), gl((size_t)p->L * 32), hl((size_t)p->L * 32);
   ti_expand(p, G_layers, G);
   ti_expand(p, Vl.data(), V);
-  qhvp_status st = qhvp_hvp(p, G.data(), V.data(), QHVP_EUCLIDEAN, cost, g.data(), h.data());
+  qhvp_status st = qhvp_hvp(p, G.data(), V.data(), QHVP_EUCLIDEAN, cost, nullptr, g.data(), h.data());
   if (st) return st;
   ti_reduce(p, g.data(), gl.data());
   ti_reduce(p, h.data(), hl.data());
@@ -1258,9 +1399,18 @@ qhvp_status qhvp_hvp_ti(qhvp_problem* p, const double* G_layers, const double* V
 
 qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
-  if (p->last_T.empty()) return fail(QHVP_ERR_INVALID, "no evaluation yet");
-  if (T) std::memcpy(T, p->last_T.data(), p->last_T.size() * sizeof(double));
-  if (Omega) std::memcpy(Omega, p->last_Om.data(), p->last_Om.size() * sizeof(double));
+  if (!p->have_eval) return fail(QHVP_ERR_INVALID, "no evaluation yet");
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  std::vector<double> tov((size_t)p->Ns * 4);
+  HIP_TRY(hipMemcpyAsync(tov.data(), p->small(p->lay.o_tov), tov.size() * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (int s = 0; s < p->Ns; ++s) {
+    if (T) { T[2 * s] = tov[4 * s]; T[2 * s + 1] = tov[4 * s + 1]; }
+    if (Omega) {
+      Omega[2 * s] = p->last_tangent ? tov[4 * s + 2] : 0.0;
+      Omega[2 * s + 1] = p->last_tangent ? tov[4 * s + 3] : 0.0;
+    }
+  }
   return QHVP_OK;
 }
 
@@ -1273,12 +1423,29 @@ qhvp_status qhvp_problem_info(const qhvp_problem* p, int* K, int* n_passes, size
   return QHVP_OK;
 }
 
-int qhvp_backward_from_outputs(const qhvp_problem* p) { return p ? p->bwd_inverse : -1; }
+int qhvp_backward_from_outputs(const qhvp_problem* p) {
+  if (!p) return -1;
+  int fl[qhvp::kFlagCount];
+  if (hipSetDevice(p->ctx->device) != hipSuccess ||
+      hipMemcpyAsync(fl, p->flags(), sizeof(fl), hipMemcpyDeviceToHost, p->stream) != hipSuccess ||
+      hipStreamSynchronize(p->stream) != hipSuccess)
+    return -1;
+  return fl[qhvp::kFlagInverse];
+}
 
-double qhvp_last_device_ms(const qhvp_problem* p) { return p ? p->last_ms : 0.0; }
+double qhvp_last_device_ms(const qhvp_problem* p) {
+  if (!p || !p->ev_fwd) return 0.0;
+  float a = 0, b = 0;
+  if (hipEventSynchronize(p->ev[p->ev_bwd ? 3 : 1]) != hipSuccess || hipEventElapsedTime(&a, p->ev[0], p->ev[1]) != hipSuccess)
+    return 0.0;
+  if (p->ev_bwd && hipEventElapsedTime(&b, p->ev[2], p->ev[3]) != hipSuccess) return 0.0;
+  return (double)a + (double)b;
+}
 
 qhvp_status qhvp_set_profiling(qhvp_problem* p, int on) {
   if (!p) return fail(QHVP_ERR_INVALID, "problem is NULL");
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  HIP_TRY(prof_collect(p));   // launches timed before the reset are dropped with the statistics
   p->profiling = on ? 1 : 0;
   for (int k = 0; k < QHVP_KERNEL_KINDS; ++k) { p->k_ms[k] = p->k_bytes[k] = p->k_flops[k] = 0; p->k_count[k] = 0; }
   return QHVP_OK;
@@ -1287,6 +1454,8 @@ qhvp_status qhvp_set_profiling(qhvp_problem* p, int on) {
 qhvp_status qhvp_kernel_stats(const qhvp_problem* p, int kind, double* total_ms, long long* launches,
                               double* alg_bytes, double* alg_flops) {
   if (!p || kind < 0 || kind >= QHVP_KERNEL_KINDS) return fail(QHVP_ERR_INVALID, "bad arguments");
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  HIP_TRY(prof_collect(const_cast<qhvp_problem*>(p)));   // waits for the timed launches
   if (total_ms) *total_ms = p->k_ms[kind];
   if (launches) *launches = p->k_count[kind];
   if (alg_bytes) *alg_bytes = p->k_bytes[kind];

@@ -68,6 +68,10 @@ struct FwdArgs {
   double* ov_part;
   int* sched;          // tile-schedule counter of this launch (zero before the launch)
   int chunk;           // set by launch_fwd: > 0 dynamic chunks of that many tiles; < 0 static ranges of -chunk tiles
+  // decisions taken on the device for this call (null: none): psi is not stored if *psi_skip != 0
+  // (the boundary already holds psi for these gates); nothing is stored if *store_if == 0
+  const int* psi_skip;
+  const int* store_if;
 };
 
 // Backward pass over the same tile structure: (a, b) at the pass output -> at the pass input
@@ -90,6 +94,10 @@ struct BwdArgs {
   // per gate (32 complex), fold passes read src_* too (no generated states)
   const void* igates;
   int turns;           // set by the launchers: 1 when two workgroups share each CU (priority turns)
+  // the launch does nothing unless *run_flag == run_when (null: always runs); the host launches both
+  // backward kernels of a pass and the device-side choice (kFlagInverse) picks one
+  const int* run_flag;
+  int run_when;
 };
 
 // Upper bound of the workgroup count of any pass kernel over `items` tiles (sizes per-workgroup
@@ -109,7 +117,60 @@ int launch_bwd_out(Prec prec, const BwdArgs& a, void* stream);
 int launch_zero_ints(int* p, int n, void* stream);
 // tov[s] = (T_s, Omega_s) = sum over tiles of ov_part.
 int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, double* tov, void* stream);
-// env[gidx[j]][0..64) = sum over wg of env_part[wg][j][0..64), for j < ng.
-int launch_reduce_env(const double* env_part, int n_wg, const PassDesc& pd, double* env, void* stream);
+// env[gidx[j]][0..64) = sum over wg of env_part[wg][j][0..64), for j < ng, over n_wg_set workgroups if
+// flag is null or *flag != 0, else over n_wg_clear (the two backward kernels have different grids).
+int launch_reduce_env(const double* env_part, int n_wg_set, int n_wg_clear, const int* flag, const PassDesc& pd,
+                      double* env, void* stream);
+
+// ---- per-call FP64 work on the device (qhvp_post.hip) ----
+// Per-call flags (ints in the workspace), written by k_prep and read by the sweeps and k_post.
+constexpr int kFlagInverse = 0;    // 1: the backward sweep runs from pass outputs (k_bwd_out)
+constexpr int kFlagStatus = 1;     // input check on the device: OR of kStat* (0: valid)
+constexpr int kFlagKeptValid = 2;  // the kept pass-boundary states belong to the gates in kept_g
+constexpr int kFlagKeep = 3;       // this sweep's gates equal kept_g bitwise: store tangents only there
+constexpr int kFlagCount = 8;
+constexpr int kStatNonFinite = 1;  // a non-finite entry in G or V
+constexpr int kStatNotUnitary = 2; // Riemannian geometry with |G^dag G - I|_F > 1e-10 for some gate
+// The backward sweep undoes gates on pass outputs only if every gate has |G|_F |G^-1|_F <= this (4 for a
+// unitary gate), so that undoing the at most kMaxGates gates of a pass loses at most a few bits.
+constexpr double kInverseCond = 8.0;
+
+// Prepare a call's gates: G_in, V_in (K*16 complex FP64, device) -> device precision gates / dirs
+// (V projected onto the tangent space at G when riem), FP64 copies g64 / v64, and, when with_inverse,
+// G^-1 (gi64, FP64) and igates (G^-1 | -G^-1 V G^-1, device precision) with flags[kFlagInverse] = 1
+// if every gate qualifies.  keep_mode (gradient / HVP sweeps): flags[kFlagKeep] = kept states valid
+// and G_in == kept_g bitwise (and !invalidate_kept); then kept_g = G_in.
+struct PrepArgs {
+  int K, prec, tangent, riem, with_inverse, keep_mode, invalidate_kept;
+  const double* G_in;
+  const double* V_in;
+  void* gates;
+  void* dirs;
+  void* igates;
+  double* g64;
+  double* v64;
+  double* gi64;
+  double* kept_g;
+  int* flags;
+};
+constexpr int kPostCost = 1, kPostDeriv = 2;
+// Post-processing: (mode & kPostCost) fidelity and cost from the overlaps tov; (mode & kPostDeriv)
+// gradient (and HVP if tangent) from the environment sums env, Riemannian if riem.  Null outputs are
+// skipped; nothing is written if flags[kFlagStatus] != 0.
+struct PostArgs {
+  int K, Ns, tangent, riem, mode;
+  const double* tov;
+  const double* env;
+  const int* flags;
+  const double* g64;
+  const double* v64;
+  const double* gi64;
+  double* cost;
+  double* fidelity;
+  double* grad;
+  double* hvp;
+};
+int launch_prep(const PrepArgs& a, void* stream);
+int launch_post(const PostArgs& a, void* stream);
 
 }  // namespace qhvp

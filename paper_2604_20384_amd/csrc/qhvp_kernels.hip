@@ -35,6 +35,7 @@
 #include <cstring>
 
 #include <type_traits>
+#include <utility>
 
 #include "qhvp_internal.h"
 
@@ -277,53 +278,57 @@ __device__ __forceinline__ void pin16(R (&v)[16]) {
 // --------------------------------------------------------------------------------------------
 // complex64 gate application on the matrix cores
 // --------------------------------------------------------------------------------------------
-// Per group (the 4 amplitudes of a qubit pair), W = [[X, 0], [Y, X]] acts on the 16 reals of
-// (p, d) as one real 16x16 matrix.  Its columns (inputs) are ordered 4*c + g and its rows
-// (outputs) 4*g + c, with g the amplitude of the pair (2*b_hi + b_lo) and c = 2*state + (0 re |
-// 1 im).  With 16 groups as the 16 columns of v_mfma_f32_16x16x4f32, MFMA step c consumes
-// component c of every amplitude, so lane (g = lane/16, col = lane%16) supplies amplitude g of
-// group col in all four steps and receives amplitude g of the result: state in, state out, same
-// lanes.  The A operand of lane l in step c is entry (l%16, 4c + l/16) of the real matrix, i.e.
-// one of +-Re, +-Im of a single complex entry u of X or Y, or 0:
-//   step 0: (Re x, Im x, Re y, Im y)[l%4]      step 1: (-Im x, Re x, -Im y, Re y)[l%4]
-//   step 2: (0, 0, Re x, Im x)[l%4]            step 3: (0, 0, -Im x, Re x)[l%4]
-// with x, y the entries [(l/4)%4][l/16] of X, Y (forward), or the conjugates of the entries
-// [l/16][(l/4)%4] (the form [[X^dag, 0], [Y^dag, X^dag]] of the backward recursion).
-__device__ __forceinline__ qv4f w_operands_xy(float2 x, float2 y, bool conj_, int lane) {
-  if (conj_) { x.y = -x.y; y.y = -y.y; }
-  const bool odd = (lane & 1) != 0, low = (lane & 2) == 0;
-  const float2 u = low ? x : y;
-  qv4f A;
-  A[0] = odd ? u.y : u.x;
-  A[1] = odd ? u.x : -u.y;
-  A[2] = low ? 0.f : (odd ? x.y : x.x);
-  A[3] = low ? 0.f : (odd ? x.x : -x.y);
-  return A;
-}
-__device__ __forceinline__ qv4f w_operands(const float2* X, const float2* Y, int e, bool conj_, int lane) {
-  return w_operands_xy(X[e], Y[e], conj_, lane);
+// Per group (the 4 amplitudes of a qubit pair), W = [[X, 0], [Y, X]] acts on the 16 reals of the
+// state pair (p, d) as one real 16x16 matrix: the block-triangular operator of App. D, with X = G,
+// Y = V in the forward recursion (Eq. fis / Eq. dfis) and X = G^dag, Y = V^dag in the backward one
+// (Eq. bis / Eq. dbis).  Each lane owns one group (lane l of wave w: group 64 w + l) and keeps its
+// 16 input reals in registers.  v_mfma_f32_4x4x1_16b_f32 multiplies, in each of its 16 blocks of 4
+// lanes, a 4-row column A by the 4 lanes' own input reals; with one block's A broadcast to all
+// blocks (CBSZ = 4, ABID = that block) an instruction adds one input real's contribution to 4
+// output reals of all 64 groups of the wave, and every lane receives its own group's outputs, so no
+// data crosses lanes.  Inputs are taken as (amplitude m, re | im) = kappa = 2 m + part; outputs in
+// quads f = 0, 1 (main state, amplitudes 2f, 2f+1, re and im each) and f = 2, 3 (tangent state).
+// The zero block (main outputs from tangent inputs) is never issued: 16 instructions for X on p,
+// 16 for Y on p and 16 for X on d, 48 against the 64 a dense 16x16 product needs.
+//
+// Operand registers: block b = 2 kappa + f (the ABID) of register x holds rows 4f..4f+3 of column
+// kappa of the real form of X ([[Re, -Im], [Im, Re]] per complex entry), register y the same of Y;
+// the X columns serve both diagonal blocks.  Lane 4 b + i holds row i of block b.
+__device__ __forceinline__ float w4_op(const float2* Z, int l, bool ct) {
+  const int blk = l >> 2, i = l & 3;
+  const int f = blk & 1, kap = blk >> 1;
+  const int o = 2 * f + (i >> 1), co = i & 1, m = kap >> 1, ci = kap & 1;
+  float2 z = ct ? Z[4 * m + o] : Z[4 * o + m];
+  if (ct) z.y = -z.y;
+  return co == ci ? z.x : (co == 0 ? -z.y : z.y);
 }
 
-// (p, d) <- W (p, d) on the 64 groups of one wave: four chains of 16 groups; all LDS reads first
-// (pinned, so that they are in flight together rather than read-and-wait one at a time), then the
-// MFMAs, then the writes.  tl: this lane's LDS offset (amplitude g of group col, chain 0); ch[c]:
-// the wave-uniform offset of chain c.  Groups beyond the tile (tiles of fewer than 2^kMaxTileBits
-// amplitudes) hold tile indices >= 2^mb only: they are transformed and written back like the others,
-// which leaves a zeroed tail zero (W 0 = 0) and never touches an index below 2^mb.
-// Byte offsets ad[c] of this lane's element of chain c, shared by every state array of the tile.
-// The lane part is made opaque so that the compiler keeps each array's LDS base as an instruction
-// offset (one add per chain for all arrays) instead of folding it into a base register per array.
-__device__ __forceinline__ void tile_addr(int tl, const int (&ch)[4], int (&ad)[4]) {
+template <int ABID>
+__device__ __forceinline__ Mfma<float>::acc_t mfma4(float a, float b, Mfma<float>::acc_t c) {
+  return __builtin_amdgcn_mfma_f32_4x4x1f32(a, b, c, 4, ABID, 0);
+}
+
+// Byte offsets ad[m] of this lane's amplitude m, shared by every state array of the tile: the lane
+// part (its group's index bits) plus the wave-uniform parts am[m] (the wave's group bits and the
+// pair bits).  The lane part is made opaque so that the compiler keeps each array's LDS base as an
+// instruction offset (one add per amplitude for all arrays) instead of folding it into a base
+// register per array.
+__device__ __forceinline__ void tile_addr(int tl, const int (&am)[4], int (&ad)[4]) {
   int tb = 8 * tl;
   asm volatile("" : "+v"(tb));
 #pragma unroll
-  for (int c = 0; c < 4; ++c) ad[c] = tb + 8 * ch[c];
+  for (int c = 0; c < 4; ++c) ad[c] = tb + 8 * am[c];
 }
 
+// (p, d) <- W (p, d) on the 64 groups of one wave.  All LDS reads first (pinned, so that they are in
+// flight together rather than read-and-wait one at a time), then the MFMAs, then the writes.  Groups
+// beyond the tile (tiles of fewer than 2^kMaxTileBits amplitudes) hold tile indices >= 2^mb only:
+// they are transformed and written back like the others, which leaves a zeroed tail zero (W 0 = 0)
+// and never touches an index below 2^mb.
 template <bool TANG>
 struct WTile {
-  float2 p[4], d[4];
-  Mfma<float>::acc_t r[4];
+  float2 p[4], d[4];            // amplitudes 0..3 of the lane's group, main and tangent state
+  Mfma<float>::acc_t r[4];      // output quads: main (0, 1), (2, 3); tangent (0, 1), (2, 3)
   __device__ __forceinline__ void load(const float2* sP, const float2* sD, const int (&ad)[4]) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -340,35 +345,56 @@ struct WTile {
       asm volatile("" ::"v"(p[0].x), "v"(p[0].y), "v"(p[1].x), "v"(p[1].y), "v"(p[2].x), "v"(p[2].y), "v"(p[3].x),
                    "v"(p[3].y));
   }
-  __device__ __forceinline__ void mfma(const qv4f A) {
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      r[c][0] = 0; r[c][1] = 0; r[c][2] = 0; r[c][3] = 0;
-      r[c] = Mfma<float>::step(A[0], p[c].x, r[c]);
-      r[c] = Mfma<float>::step(A[1], p[c].y, r[c]);
-      if (TANG) {
-        r[c] = Mfma<float>::step(A[2], d[c].x, r[c]);
-        r[c] = Mfma<float>::step(A[3], d[c].y, r[c]);
-      }
+  // Main-input column kappa (all four output quads: X and Y on p), then the tangent-input columns
+  // (X on d, tangent quads only): the main outputs are complete after the first 32 instructions, so
+  // their stores overlap the last 16, and the tangent inputs are needed last.
+  template <int KAP>
+  __device__ __forceinline__ void column_p(float x, float y) {
+    const float ip = (KAP & 1) ? p[KAP >> 1].y : p[KAP >> 1].x;
+    r[0] = mfma4<2 * KAP>(x, ip, r[0]);
+    r[1] = mfma4<2 * KAP + 1>(x, ip, r[1]);
+    if constexpr (TANG) {
+      r[2] = mfma4<2 * KAP>(y, ip, r[2]);
+      r[3] = mfma4<2 * KAP + 1>(y, ip, r[3]);
     }
+  }
+  template <int KAP>
+  __device__ __forceinline__ void column_d(float x) {
+    const float id = (KAP & 1) ? d[KAP >> 1].y : d[KAP >> 1].x;
+    r[2] = mfma4<2 * KAP>(x, id, r[2]);
+    r[3] = mfma4<2 * KAP + 1>(x, id, r[3]);
+  }
+  template <int... K>
+  __device__ __forceinline__ void columns(float x, float y, std::integer_sequence<int, K...>) {
+    (column_p<K>(x, y), ...);
+    if constexpr (TANG) (column_d<K>(x), ...);
+  }
+  __device__ __forceinline__ void mfma(float x, float y) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { r[c][0] = 0; r[c][1] = 0; r[c][2] = 0; r[c][3] = 0; }
+    columns(x, y, std::make_integer_sequence<int, 8>{});
   }
   __device__ __forceinline__ void store(float2* sP, float2* sD, const int (&ad)[4]) const {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      *(float2*)((char*)sP + ad[c]) = make_float2(r[c][0], r[c][1]);
-      if (TANG) *(float2*)((char*)sD + ad[c]) = make_float2(r[c][2], r[c][3]);
+      const Mfma<float>::acc_t& q = r[c >> 1];
+      *(float2*)((char*)sP + ad[c]) = (c & 1) ? make_float2(q[2], q[3]) : make_float2(q[0], q[1]);
+      if (TANG) {
+        const Mfma<float>::acc_t& u = r[2 + (c >> 1)];
+        *(float2*)((char*)sD + ad[c]) = (c & 1) ? make_float2(u[2], u[3]) : make_float2(u[0], u[1]);
+      }
     }
   }
 };
 
 template <bool TANG>
-__device__ __forceinline__ void apply_w_mfma(const qv4f A, float2* sP, float2* sD, int tl, const int (&ch)[4]) {
+__device__ __forceinline__ void apply_w_mfma(float x, float y, float2* sP, float2* sD, int tl, const int (&am)[4]) {
   int ad[4];
-  tile_addr(tl, ch, ad);
+  tile_addr(tl, am, ad);
   WTile<TANG> w;
   w.load(sP, sD, ad);
   w.pin();
-  w.mfma(A);
+  w.mfma(x, y);
   w.store(sP, sD, ad);
 }
 
@@ -396,65 +422,33 @@ __device__ __forceinline__ void stage_offsets(const PassDesc& pd, int* sOff, int
 struct GateOff {
   int go[8], ao[2];
 };
-// complex64 W operand tables.  Lane l's four A operands of a gate (w_operands_xy) are
-// (A0, A1) = T_odd(u) and (A2, A3) = low ? 0 : T_odd(x), with T_0(v) = (Re v, -Im v),
-// T_1(v) = (Im v, Re v), u = low ? x : y and odd, low = lane bit 0 set, lane bit 1 clear.  The
-// table of one W holds T_0(x), T_1(x), T_0(y), T_1(y) for the 16 entries (kOpTab float2); with a
-// zero entry in the pass's table block, each lane loads its operand pairs directly, from offsets
-// that do not change (OpLane), instead of selecting them per gate.
-constexpr int kOpTab = 64;
-struct OpLane {
-  int o01, o23;   // float2 offsets of (A0, A1) and (A2, A3) within a W table (o23: the zero entry)
-  __device__ __forceinline__ OpLane(int lane, int e, int zero) {
-    const int odd = lane & 1, low = (lane & 2) == 0;
-    o01 = ((low ? 0 : 2) + odd) * 16 + e;
-    o23 = low ? zero : odd * 16 + e;
-  }
-};
-// Table entry t (0 .. kOpTab) of a W with entries x = X[e], y = Y[e] (t = 16 q + e).
-__device__ __forceinline__ float2 op_entry(float2 x, float2 y, int t) {
-  const int q = t >> 4;
-  const float2 v = q < 2 ? x : y;
-  return (q & 1) ? make_float2(v.y, v.x) : make_float2(v.x, -v.y);
-}
-
-// What one backward step of k_bwd_out reads from the per-pass LDS tables, loaded ahead so that the
-// step does not start with a chain of LDS round trips: the gate's offsets (made scalar with
-// readfirstlane when used) and, for complex64, this lane's operand pairs of W^dag (ay) and of the
-// inverse (ax) (the forward kernel: of W, in ax).
+// complex64 operand tables of the gate applications (w4_op): per gate slot and lane, the x and y
+// operands of each W the kernel applies, built once per launch, so that a gate step loads them with
+// one LDS read (k_fwd: W = [[G, 0], [V, G]]; k_bwd_out: W^dag = [[G^dag, 0], [V^dag, G^dag]] and the
+// inverse [[G^-1, 0], [Y, G^-1]]).
+//
+// What one gate step reads from the per-pass LDS tables, loaded ahead so that the step does not start
+// with a chain of LDS round trips: the gate's offsets (made scalar with readfirstlane when used) and,
+// for complex64, this lane's operands (k_fwd: x, y of W in op[0], op[1]; k_bwd_out: x, y of W^dag,
+// then x, y of the inverse) and packed lane offsets.
 struct StepRaw {
   int off[kOffs];
-  float2 ay[2], ax[2];
+  qv4f op;
   int lanep;      // complex64: this lane's packed offsets of the gate (lane_offsets)
 };
-// k_bwd_out's table block per gate slot: W^dag table | inverse table | zero entry.
-constexpr int kBwdOpSlot = 2 * kOpTab + 2;
-__device__ __forceinline__ void load_gates(const float2* sGV, int j, const OpLane& ly, const OpLane& lx, StepRaw& r) {
-  r.ay[0] = sGV[kBwdOpSlot * j + ly.o01];
-  r.ay[1] = sGV[kBwdOpSlot * j + ly.o23];
-  r.ax[0] = sGV[kBwdOpSlot * j + kOpTab + lx.o01];   // lx: offsets within the inverse table
-  r.ax[1] = sGV[kBwdOpSlot * j + kOpTab + lx.o23];
-}
-// k_fwd's table block per gate slot: W table | zero entry.
-constexpr int kFwdOpSlot = kOpTab + 2;
-__device__ __forceinline__ void load_fwd_step(const int* sOff, const float2* sGV, const int* sLane, int j, int lane,
-                                              const OpLane& lx, StepRaw& r) {
+__device__ __forceinline__ void load_fwd_step(const int* sOff, const float2* sW, const int* sLane, int j, int lane,
+                                              StepRaw& r) {
 #pragma unroll
   for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
-  r.ax[0] = sGV[kFwdOpSlot * j + lx.o01];
-  r.ax[1] = sGV[kFwdOpSlot * j + lx.o23];
+  const float2 w = sW[64 * j + lane];
+  r.op[0] = w.x; r.op[1] = w.y; r.op[2] = 0.f; r.op[3] = 0.f;
   r.lanep = sLane[64 * j + lane];
 }
-__device__ __forceinline__ void load_step(const int* sOff, const float2* sGV, int j, const OpLane& ly,
-                                          const OpLane& lx, bool with_gates, StepRaw& r) {
+__device__ __forceinline__ void load_step(const int* sOff, const qv4f* sW, int j, int lane, bool with_gates,
+                                          StepRaw& r) {
 #pragma unroll
   for (int i = 0; i < kOffs; ++i) r.off[i] = sOff[kOffs * j + i];
-  if (with_gates) load_gates(sGV, j, ly, lx, r);
-}
-__device__ __forceinline__ qv4f op_quad(const float2 (&a)[2]) {
-  qv4f A;
-  A[0] = a[0].x; A[1] = a[0].y; A[2] = a[1].x; A[3] = a[1].y;
-  return A;
+  if (with_gates) r.op = sW[64 * j + lane];
 }
 
 // Padded LDS indices of the 4 amplitudes of group g (2*b_hi + b_lo order).
@@ -481,26 +475,31 @@ __device__ __forceinline__ GateOff gate_offsets(const int* sOff, int j) {
   return o;
 }
 
-// LDS offsets of gate slot j for the MFMA gate application of this lane / wave (group index
-// 64*wave + 16*c + col, amplitude g), from the pass constants goff / aoff.
-__device__ __forceinline__ void w_offsets(const GateOff& o, int wave, int lane, int& tl, int (&ch)[4]) {
-  const int* go = o.go;
-  const int* ao = o.ao;
-  const int col = lane & 15, g = lane >> 4;
-  tl = bitsel(col, 0, go[0]) + bitsel(col, 1, go[1]) + bitsel(col, 2, go[2]) + bitsel(col, 3, go[3]) +
-       bitsel(g, 0, ao[0]) + bitsel(g, 1, ao[1]);
-  const int wv = bitsel(wave, 0, go[6]) + bitsel(wave, 1, go[7]);
-  ch[0] = wv;
-  ch[1] = wv + go[4];
-  ch[2] = wv + go[5];
-  ch[3] = wv + go[4] + go[5];
+// Wave-uniform offsets of the 4 amplitudes of the W tile: the wave's group bits 6, 7 and the pair
+// bits of the gate.
+__device__ __forceinline__ void w_amps(const GateOff& o, int wave, int (&am)[4]) {
+  const int wv = bitsel(wave, 0, o.go[6]) + bitsel(wave, 1, o.go[7]);
+  am[0] = wv;
+  am[1] = wv + o.ao[0];
+  am[2] = wv + o.ao[1];
+  am[3] = wv + o.ao[0] + o.ao[1];
+}
+// LDS offsets of gate slot j for the MFMA gate application of this lane / wave (group 64 wave + lane:
+// its bits 0..5 are the lane's), from the pass constants goff / aoff.
+__device__ __forceinline__ void w_offsets(const GateOff& o, int wave, int lane, int& tl, int (&am)[4]) {
+  tl = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) tl += bitsel(lane, i, o.go[i]);
+  w_amps(o, wave, am);
 }
 
 // complex64 per-lane offsets of a pass, computed once per launch (they depend on the gate slot and
 // the lane only): sLane[64 j + l] packs, for lane l and gate slot j, the byte index of the lane's
 // environment operand (low 16 bits; elements of R, second state array included) and 8x the
-// element index of its W-tile element (high 16 bits), both without the wave-uniform parts.
-// The same bit selects as w_offsets, and the environment operand layout of k_bwd_out.
+// element index of its group in the W tile (high 16 bits), both without the wave-uniform parts.
+// The environment operand of lane l is real part cri of amplitude cidx of state cst of group sub
+// (comp = l % 16 = 8 cst + 4 cri + cidx, sub = l / 16: group bits 0, 1), the layout of k_bwd_out's
+// MFMA operands (A: rows = lane % 16, B: columns = lane % 16).
 __device__ __forceinline__ int lane_offsets(const PassDesc& pd, int j, int l, int tsp, bool tang) {
   const int* go = pd.goff[j];
   const int* ao = pd.aoff[j];
@@ -508,26 +507,17 @@ __device__ __forceinline__ int lane_offsets(const PassDesc& pd, int j, int l, in
   const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
   const int tl = bitsel(sub, 0, go[0]) + bitsel(sub, 1, go[1]) + bitsel(cidx, 0, ao[0]) + bitsel(cidx, 1, ao[1]);
   const int eb = 4 * (2 * (tang ? cst : 0) * tsp + cri + 2 * tl);
-  const int col = l & 15, g = l >> 4;
-  const int tw = bitsel(col, 0, go[0]) + bitsel(col, 1, go[1]) + bitsel(col, 2, go[2]) + bitsel(col, 3, go[3]) +
-                 bitsel(g, 0, ao[0]) + bitsel(g, 1, ao[1]);
+  int tw = 0;
+#pragma unroll
+  for (int i = 0; i < 6; ++i) tw += bitsel(l, i, go[i]);
   return eb | ((8 * tw) << 16);
 }
-// Wave-uniform chain offsets of the W tile (group bits 4, 5 and the wave's bits 6, 7).
-__device__ __forceinline__ void w_chains(const GateOff& o, int wave, int (&ch)[4]) {
-  const int* go = o.go;
-  const int wv = bitsel(wave, 0, go[6]) + bitsel(wave, 1, go[7]);
-  ch[0] = wv;
-  ch[1] = wv + go[4];
-  ch[2] = wv + go[5];
-  ch[3] = wv + go[4] + go[5];
-}
 // Tile byte offsets ad[c] from the lane's packed offsets (high half: 8x its element index).
-__device__ __forceinline__ void tile_addr_packed(int lanep, const int (&ch)[4], int (&ad)[4]) {
+__device__ __forceinline__ void tile_addr_packed(int lanep, const int (&am)[4], int (&ad)[4]) {
   int tb = (int)((unsigned)lanep >> 16);
   asm volatile("" : "+v"(tb));
 #pragma unroll
-  for (int c = 0; c < 4; ++c) ad[c] = tb + 8 * ch[c];
+  for (int c = 0; c < 4; ++c) ad[c] = tb + 8 * am[c];
 }
 
 // Stage the G (and V) entries of the pass's gates in LDS: sGV[32 j + e] = G_(gidx j)[e],
@@ -541,21 +531,14 @@ __device__ __forceinline__ void stage_gates(const PassDesc& pd, const float2* G,
   }
 }
 
-// The forward kernel's operand tables (complex64): per gate slot j, the table of W = [[G, 0], [V, G]]
-// (V = 0 without tangent) and a zero entry.  Visible after the next barrier.
+// The forward kernel's operand table (complex64): per gate slot j and lane l, the operands x, y of
+// W = [[G, 0], [V, G]] (y = 0 without tangent).  Visible after the next barrier.
 template <bool TANG>
-__device__ __forceinline__ void stage_fwd_op_tables(const PassDesc& pd, const float2* G, const float2* V, float2* sGV,
+__device__ __forceinline__ void stage_fwd_op_tables(const PassDesc& pd, const float2* G, const float2* V, float2* sW,
                                                     int tid) {
-  for (int j = 0; j < pd.ng; ++j) {
-    const int k = pd.gidx[j];
-    if (tid < kOpTab) {
-      const int e = tid & 15;
-      const float2 x = G[16 * k + e];
-      const float2 y = TANG ? V[16 * k + e] : make_float2(0.f, 0.f);
-      sGV[kFwdOpSlot * j + tid] = op_entry(x, y, tid);
-    } else if (tid < kFwdOpSlot) {
-      sGV[kFwdOpSlot * j + tid] = make_float2(0.f, 0.f);
-    }
+  for (int i = tid; i < pd.ng * 64; i += kThreads) {
+    const int j = i >> 6, l = i & 63, k = pd.gidx[j];
+    sW[i] = make_float2(w4_op(G + 16 * k, l, false), TANG ? w4_op(V + 16 * k, l, false) : 0.f);
   }
 }
 
@@ -598,7 +581,7 @@ __global__ void __launch_bounds__(kThreads)
   __shared__ __attribute__((aligned(16))) T sD[TANG ? LD::TSP : 1];
   __shared__ T sU[2 * kMaxQubits];
   __shared__ double sRed[kThreads / 64][4];
-  __shared__ float2 sGV[kF32 ? kMaxGates * kFwdOpSlot : 1];
+  __shared__ float2 sW[kF32 ? kMaxGates * 64 : 1];   // per gate slot and lane: operands x, y of W
   __shared__ int sLane[kF32 ? kMaxGates * 64 : 1];
   __shared__ int sOff[kMaxGates * kOffs];
   __shared__ int sSch[2];
@@ -622,17 +605,17 @@ __global__ void __launch_bounds__(kThreads)
   const bool gen = (srcP == nullptr);
   const bool ovl = (a.ov_part != nullptr);
   // psi and dpsi are stored independently: a tangent sweep may leave psi in a boundary buffer that
-  // already holds it (same gates) and store dpsi only
-  const bool stP = dstP != nullptr, stD = TANG && dstD != nullptr;
+  // already holds it (same gates) and store dpsi only; both decisions can come from the device
+  const bool st_ok = a.store_if == nullptr || *a.store_if != 0;
+  const bool stP = st_ok && dstP != nullptr && !(a.psi_skip != nullptr && *a.psi_skip != 0);
+  const bool stD = st_ok && TANG && dstD != nullptr;
   const unsigned imask = (unsigned)pd.imask;
   const bool wl = pd.wave_local != 0;
-  const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);   // entry of X, Y behind this lane's operands
-  const OpLane lx(lane, e_fwd, kOpTab);
   static_assert(NG >= 0 && NG <= kMaxGates && (NG > 0) == kF32, "complex64 instances have a fixed gate count");
   if (NG > 0 && ng != NG) return;   // the launcher picks the instance by the pass's gate count
 
   if constexpr (kF32) {
-    stage_fwd_op_tables<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
+    stage_fwd_op_tables<TANG>(pd, (const float2*)G, (const float2*)V, sW, tid);
     for (int i = tid; i < ng * 64; i += kThreads) sLane[i] = lane_offsets(pd, i >> 6, i & 63, LD::TSP, TANG);
   }
   stage_offsets(pd, sOff, tid);
@@ -687,7 +670,7 @@ __global__ void __launch_bounds__(kThreads)
   StepRaw nxt;
   if constexpr (kF32) {
     __syncthreads();   // the staged tables
-    load_fwd_step(sOff, sGV, sLane, 0, lane, lx, nxt);
+    load_fwd_step(sOff, sW, sLane, 0, lane, nxt);
   }
 
   while (c < nch) {
@@ -742,15 +725,14 @@ __global__ void __launch_bounds__(kThreads)
         // this step's tables were loaded one step ahead; load the next step's (the next tile's
         // first after the last gate: the tables do not change between tiles)
         const StepRaw cur = nxt;
-        load_fwd_step(sOff, sGV, sLane, j + 1 < NG ? j + 1 : 0, lane, lx, nxt);
+        load_fwd_step(sOff, sW, sLane, j + 1 < NG ? j + 1 : 0, lane, nxt);
         const GateOff O = gate_offsets_raw(cur.off);
-        int ch[4], ad[4];
-        w_chains(O, wave, ch);
-        tile_addr_packed(cur.lanep, ch, ad);
+        int am[4], ad[4];
+        w_amps(O, wave, am);
+        tile_addr_packed(cur.lanep, am, ad);
         WTile<TANG> w;
         w.load(sP, sD, ad);
-        w.pin();
-        w.mfma(op_quad(cur.ax));
+        w.mfma(cur.op[0], cur.op[1]);
         w.store(sP, sD, ad);
       } else {
         const GateOff O = gate_offsets(sOff, j);
@@ -988,6 +970,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   __shared__ float2 sGV[kF32 ? kMaxGates * 32 : 1];
   __shared__ int sOff[kMaxGates * kOffs];
 
+  if (a.run_flag != nullptr && *a.run_flag != a.run_when) return;   // the other backward kernel runs
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -1008,8 +991,6 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   const bool gen = (srcP == nullptr);
   const unsigned imask = (unsigned)pd.imask;
   const bool wl = pd.wave_local != 0;
-  const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);
-  const int e_bwd = 4 * (lane >> 4) + ((lane >> 2) & 3);
 
   if constexpr (kF32) stage_gates<TANG>(pd, (const float2*)G, (const float2*)V, sGV, tid);
   stage_offsets(pd, sOff, tid);
@@ -1165,10 +1146,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
         pin16(bop[j]);
         if (j + 1 < ng) {
           if constexpr (kF32) {
-            int tw, ch[4];
-            w_offsets(O, uwave, lane, tw, ch);
-            const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_fwd, false, lane);
-            apply_w_mfma<TANG>(A, sX, sX + TSP, tw, ch);
+            int tw, am[4];
+            w_offsets(O, uwave, lane, tw, am);
+            const float wx = w4_op(sGV + 32 * j, lane, false);
+            const float wy = TANG ? w4_op(sGV + 32 * j + 16, lane, false) : 0.f;
+            apply_w_mfma<TANG>(wx, wy, sX, sX + TSP, tw, am);
           } else {
             const auto Gk = opaque(G + 16 * pd.gidx[j]);
             const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
@@ -1218,10 +1200,11 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
           for (int r = 0; r < 4; ++r) acc[0][r] = 0;
         }
         if constexpr (kF32) {
-          int tw, ch[4];
-          w_offsets(O, uwave, lane, tw, ch);
-          const qv4f A = w_operands(sGV + 32 * j, sGV + 32 * j + 16, e_bwd, true, lane);
-          apply_w_mfma<TANG>(A, sY, sY + TSP, tw, ch);
+          int tw, am[4];
+          w_offsets(O, uwave, lane, tw, am);
+          const float wx = w4_op(sGV + 32 * j, lane, true);
+          const float wy = TANG ? w4_op(sGV + 32 * j + 16, lane, true) : 0.f;
+          apply_w_mfma<TANG>(wx, wy, sY, sY + TSP, tw, am);
         } else {
           const auto Gk = opaque(G + 16 * pd.gidx[j]);
           const auto Vk = opaque(TANG ? V + 16 * pd.gidx[j] : G);
@@ -1297,9 +1280,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   __shared__ double sAcc[kF32 ? MAXG * 256 : 1];
   __shared__ int sLane[kF32 ? MAXG * 64 : 1];
   __shared__ __attribute__((aligned(16))) float sStg[kF32 ? 4 * MAXG * 256 : 1];
-  __shared__ float2 sGV[kF32 ? kMaxGates * kBwdOpSlot : 1];   // per gate slot: W^dag and inverse operand tables
+  __shared__ qv4f sW[kF32 ? kMaxGates * 64 : 1];   // per gate slot and lane: x, y of W^dag, x, y of the inverse
   __shared__ int sOff[kMaxGates * kOffs];
 
+  if (a.run_flag != nullptr && *a.run_flag != a.run_when) return;   // the other backward kernel runs
   const PassDesc& pd = a.pd;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -1319,35 +1303,22 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   const T* __restrict__ phi0 = (const T*)a.phi0;
   const unsigned imask = (unsigned)pd.imask;
   const bool wl = pd.wave_local != 0;
-  const int e_fwd = 4 * ((lane >> 2) & 3) + (lane >> 4);
-  const int e_bwd = 4 * (lane >> 4) + ((lane >> 2) & 3);
-  // zero entry: 2 kOpTab from the slot start, i.e. kOpTab from the inverse table's start
-  const OpLane ly(lane, e_bwd, 2 * kOpTab), lx(lane, e_fwd, kOpTab);
   // complex64 instances are compiled for exactly MAXG gates (the launcher picks the instance by the
   // pass's gate count), so that the gate steps are straight-line code
   if (kF32 && ng != MAXG) return;
 
   if constexpr (kF32) {
-    // operand tables: W^dag = [[G^dag, 0], [V^dag, G^dag]] (its entries enter conjugated, as in
-    // w_operands_xy with conj_) and the inverse [[G^-1, 0], [Y, G^-1]], then a zero entry
-    for (int j = 0; j < ng; ++j) {
-      const int k = pd.gidx[j];
-      if (tid < 2 * kOpTab) {
-        const int t = tid & (kOpTab - 1), e = t & 15;
-        float2 x, y = make_float2(0.f, 0.f);
-        if (tid < kOpTab) {
-          x = ((const float2*)G)[16 * k + e];
-          if (TANG) y = ((const float2*)V)[16 * k + e];
-          x.y = -x.y;
-          y.y = -y.y;
-        } else {
-          x = ((const float2*)GI)[32 * k + e];
-          if (TANG) y = ((const float2*)GI)[32 * k + 16 + e];
-        }
-        sGV[kBwdOpSlot * j + tid] = op_entry(x, y, t);
-      } else if (tid < kBwdOpSlot) {
-        sGV[kBwdOpSlot * j + tid] = make_float2(0.f, 0.f);
-      }
+    // operand tables: W^dag = [[G^dag, 0], [V^dag, G^dag]] and the inverse [[G^-1, 0], [Y, G^-1]]
+    for (int i = tid; i < ng * 64; i += kThreads) {
+      const int j = i >> 6, l = i & 63, k = pd.gidx[j];
+      const float2* Gk = (const float2*)G + 16 * k;
+      const float2* GIk = (const float2*)GI + 32 * k;
+      qv4f w;
+      w[0] = w4_op(Gk, l, true);
+      w[1] = TANG ? w4_op((const float2*)V + 16 * k, l, true) : 0.f;
+      w[2] = w4_op(GIk, l, false);
+      w[3] = TANG ? w4_op(GIk + 16, l, false) : 0.f;
+      sW[i] = w;
     }
     for (int i = tid; i < ng * 64; i += kThreads) sLane[i] = lane_offsets(pd, i >> 6, i & 63, TSP, TANG);
   }
@@ -1449,10 +1420,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       // states its predecessor stored, and the arithmetic and its order are those of the plain
       // sequence: only the issue order changes.  Offsets and gate entries are loaded two steps ahead.
       StepRaw rw[2];
-      load_step(sOff, sGV, MAXG - 1, ly, lx, true, rw[(MAXG - 1) & 1]);
+      load_step(sOff, sW, MAXG - 1, lane, true, rw[(MAXG - 1) & 1]);
       rw[(MAXG - 1) & 1].lanep = sLane[64 * (MAXG - 1) + lane];
       if (MAXG > 1) {
-        load_step(sOff, sGV, MAXG > 1 ? MAXG - 2 : 0, ly, lx, true, rw[(MAXG - 2) & 1]);
+        load_step(sOff, sW, MAXG > 1 ? MAXG - 2 : 0, lane, true, rw[(MAXG - 2) & 1]);
         rw[(MAXG - 2) & 1].lanep = sLane[64 * (MAXG > 1 ? MAXG - 2 : 0) + lane];
       }
       R av[16], bx[16];
@@ -1476,9 +1447,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       };
       // W operands of a gate (the tile addresses ad are kept for the stores)
       auto w_reads = [&](const StepRaw& st, const GateOff& O, bool ab, bool xs) {
-        int ch[4];
-        w_chains(O, uwave, ch);
-        tile_addr_packed(st.lanep, ch, ad);
+        int am[4];
+        w_amps(O, uwave, am);
+        tile_addr_packed(st.lanep, am, ad);
         if (ab) wy.load(sY, sY + TSP, ad);
         if (xs) wx.load(sX, sX + TSP, ad);
       };
@@ -1492,14 +1463,12 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         const StepRaw& cur = rw[j & 1];
         const bool undo_ab = j > 0 || a.store_ab;   // (a, b) at the pass input are needed
         // region A
-        if (undo_ab) wy.pin();
-        if (j > 0) wx.pin();
         if (undo_ab) {
-          wy.mfma(op_quad(cur.ay));
+          wy.mfma(cur.op[0], cur.op[1]);
           wy.store(sY, sY + TSP, ad);
         }
         if (j > 0) {
-          wx.mfma(op_quad(cur.ax));
+          wx.mfma(cur.op[2], cur.op[3]);
           wx.store(sX, sX + TSP, ad);
         }
         if (wl && j > 0) wave_sync();
@@ -1521,7 +1490,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         if (j > 0) {
           env_reads(rw[(j + 1) & 1], On);
           if (j > 1) {   // gate j's are done
-            load_step(sOff, sGV, j > 1 ? j - 2 : 0, ly, lx, true, rw[j & 1]);
+            load_step(sOff, sW, j > 1 ? j - 2 : 0, lane, true, rw[j & 1]);
             rw[j & 1].lanep = sLane[64 * (j > 1 ? j - 2 : 0) + lane];
           }
         }
@@ -1531,7 +1500,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
     for (int j = MAXG - 1; j >= 0; --j) {
       if (j < ng) {
         StepRaw cur;
-        load_step(sOff, sGV, j, ly, lx, false, cur);
+        load_step(sOff, sW, j, lane, false, cur);
         const GateOff O = gate_offsets_raw(cur.off);
         const int* go = O.go;
         const int tl = bitsel(sub, 0, cur.off[0]) + bitsel(sub, 1, cur.off[1]) + bitsel(cidx, 0, cur.off[8]) +
@@ -1626,10 +1595,12 @@ __global__ void __launch_bounds__(256) k_reduce_overlaps(const double* __restric
 
 // One block per gate slot j: thread t sums workgroups wg = t/64, t/64 + 16, ... for output t%64,
 // then the 16 partial sums are added in a fixed order.
-__global__ void __launch_bounds__(1024) k_reduce_env(const double* __restrict__ env_part, int n_wg, PassDesc pd,
+__global__ void __launch_bounds__(1024) k_reduce_env(const double* __restrict__ env_part, int n_wg_set,
+                                                     int n_wg_clear, const int* flag, PassDesc pd,
                                                      double* __restrict__ env) {
   __shared__ double red[16][kEnvVals];
   const int j = blockIdx.x;
+  const int n_wg = (flag == nullptr || *flag != 0) ? n_wg_set : n_wg_clear;
   const int o = threadIdx.x & 63, chunk = threadIdx.x >> 6;
   double v = 0;
   for (int wg = chunk; wg < n_wg; wg += 16) v += env_part[((long long)wg * kMaxGates + j) * kEnvVals + o];
@@ -1832,8 +1803,10 @@ int launch_reduce_overlaps(const double* ov_part, int n_samples, int tiles, doub
   return (int)hipGetLastError();
 }
 
-int launch_reduce_env(const double* env_part, int n_wg, const PassDesc& pd, double* env, void* stream) {
-  hipLaunchKernelGGL(k_reduce_env, dim3(pd.ng), dim3(1024), 0, (hipStream_t)stream, env_part, n_wg, pd, env);
+int launch_reduce_env(const double* env_part, int n_wg_set, int n_wg_clear, const int* flag, const PassDesc& pd,
+                      double* env, void* stream) {
+  hipLaunchKernelGGL(k_reduce_env, dim3(pd.ng), dim3(1024), 0, (hipStream_t)stream, env_part, n_wg_set, n_wg_clear,
+                     flag, pd, env);
   return (int)hipGetLastError();
 }
 

@@ -12,6 +12,7 @@ import numpy as np
 import pytest
 
 from oracle import circuit, sv
+from parity import assert_close, assert_fidelity
 from paper_2604_20384_amd.inputs import haar_unitary, make_problem, random_tangent
 
 pytestmark = pytest.mark.gpu
@@ -52,8 +53,8 @@ def test_batch_equals_fresh_single_calls(gpu, precision, ckpt):
         assert np.array_equal(hm, H[m]), m
     psi, phi = circuit.labels(p.uref, p.samples, p.n, p.L_ref)
     ref = sv.evaluate(psi, phi, p.G, Vs[2], p.n, p.L)
-    assert _rel(g, ref["grad"]) <= TOL[precision]
-    assert _rel(H[2], ref["hvp"]) <= TOL[precision]
+    assert_close(g, ref["grad"], TOL[precision], "fixed-G grad")
+    assert_close(H[2], ref["hvp"], TOL[precision], "fixed-G hvp")
     # a second batch at the same G finds the states kept from the first one
     c2, g2, H2 = gp.hvp_batch(p.G, Vs[::-1])
     assert c2 == c and np.array_equal(g2, g) and np.array_equal(H2, H[::-1])

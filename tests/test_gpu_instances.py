@@ -6,12 +6,12 @@ meaning if the planner changes), run as a complex64 HVP and compared with the or
 (n = 2, 5, 6: one tile per sample, workgroup barriers between gates) and full wave-local tiles
 (n >= 11).
 """
-import numpy as np
 import pytest
 
 from oracle import circuit, sv
 from paper_2604_20384_amd.api import plan
 from paper_2604_20384_amd.inputs import make_problem
+from parity import assert_close, assert_fidelity
 
 pytestmark = pytest.mark.gpu
 
@@ -32,9 +32,9 @@ def test_c64_instances_against_oracle(gpu, n, L, ns, counts):
     for ckpt in (0, 1):
         gp = Problem(p.n, p.L, p.uref, p.samples, L_ref=p.L_ref, precision="c64", ckpt_every=ckpt)
         c, g, h = gp.hvp(p.G, p.V)
+        F = gp.last_fidelity
         assert gp.backward_from_outputs
         gp.close()
-        F = 1 - c
-        assert abs(F - ref["fidelity"]) / ref["fidelity"] <= 1e-5
-        for got, want in ((g, ref["grad"]), (h, ref["hvp"])):
-            assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 1e-5, (n, L, ckpt)
+        assert_fidelity(F, ref["fidelity"], 1e-5, (n, L, ckpt))
+        assert_close(g, ref["grad"], 1e-5, (n, L, ckpt, "grad"))
+        assert_close(h, ref["hvp"], 1e-5, (n, L, ckpt, "hvp"))

@@ -1,0 +1,61 @@
+"""Parity above the headline size: n = 21 and 22 (the serving mix reaches 22) against the oracle,
+and n = 24 through the per-sample overlaps the oracle computes one sample at a time.
+
+n = 21, 22: L = 6, 2 samples, complex128 (1e-10) and complex64 (1e-5), every pass boundary kept
+(ckpt 0) and layer checkpointing (ckpt 1), fidelity, gradient and HVP compared globally and gate by
+gate.  n = 24: L = 4, 2 samples, complex64; the oracle cannot cache every gate's state at this size,
+so the sampled overlaps T_s = phi_s^dag G psi_s and the size-independent Euler identity are checked.
+"""
+import numpy as np
+import pytest
+
+from oracle import circuit, sv
+from parity import assert_close, assert_fidelity
+from paper_2604_20384_amd.inputs import make_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 1e-5}
+
+
+@pytest.mark.parametrize("n", [21, 22])
+def test_large_n_against_oracle(gpu, n):
+    import torch
+
+    from paper_2604_20384_amd.api import Problem
+    L, ns = 6, 2
+    p = make_problem(n, L, ns, seed=300 + n)
+    psi, phi = circuit.labels(p.uref, p.samples, n, p.L_ref)
+    ref = sv.evaluate(psi, phi, p.G, p.V, n, L, batch=1)
+    for precision in ("c128", "c64"):
+        for ckpt in (0, 1):
+            torch.cuda.empty_cache()
+            gp = Problem(n, L, p.uref, p.samples, L_ref=p.L_ref, precision=precision, ckpt_every=ckpt)
+            c, g, h = gp.hvp(p.G, p.V)
+            what = f"n={n} {precision} ckpt {ckpt}"
+            eF = assert_fidelity(gp.last_fidelity, ref["fidelity"], TOL[precision], what)
+            eg = assert_close(g, ref["grad"], TOL[precision], what + " grad")
+            eh = assert_close(h, ref["hvp"], TOL[precision], what + " hvp")
+            print(f"{what}: rel err F {eF:.2e} grad {eg[0]:.2e}/{eg[1]:.2e} hvp {eh[0]:.2e}/{eh[1]:.2e}")
+            gp.close()
+
+
+def test_n24_sampled_overlaps(gpu):
+    import torch
+
+    from paper_2604_20384_amd.api import Problem
+    n, L, ns = 24, 4, 2
+    p = make_problem(n, L, ns, seed=324)
+    torch.cuda.empty_cache()
+    gp = Problem(n, L, p.uref, p.samples, L_ref=p.L_ref, precision="c64", ckpt_every=0)
+    c, g, h = gp.hvp(p.G, p.V)
+    F = gp.last_fidelity
+    T, _ = gp.overlaps()
+    gp.close()
+    for s in range(ns):
+        psi, phi = circuit.labels(p.uref, p.samples[s:s + 1], n, p.L_ref)
+        Ts = np.vdot(phi[0], circuit.apply_circuit(psi[0][:, None], p.G, n, L)[:, 0])
+        assert abs(T[s] - Ts) <= 1e-5 * abs(Ts), (s, T[s], Ts)
+    assert abs(F - np.mean(np.abs(T) ** 2)) <= 1e-12 * F
+    e = np.einsum("kij,kij->k", np.conj(g), p.G)
+    assert np.max(np.abs(e + 2 * F)) <= 1e-5 * 2 * F

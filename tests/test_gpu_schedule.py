@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 from oracle import circuit, sv
+from parity import assert_close, assert_fidelity
 from paper_2604_20384_amd.inputs import make_problem
 
 pytestmark = pytest.mark.gpu
@@ -31,9 +32,10 @@ def _gpu(precision):
     p = make_problem(N, L, NS, seed=SEED)
     gp = Problem(N, L, p.uref, p.samples, L_ref=p.L_ref, precision=precision, ckpt_every=0)
     out = gp.hvp(p.G, p.V)
+    F = gp.last_fidelity
     T, Om = gp.overlaps()
     gp.close()
-    return out, T, Om
+    return out, F, T, Om
 
 
 @pytest.fixture(scope="module")
@@ -45,18 +47,19 @@ def oracle_ref():
 
 @pytest.mark.parametrize("precision", ["c128", "c64"])
 def test_dynamic_schedule_matches_oracle_and_static_split(gpu, oracle_ref, precision):
-    (c, g, h), T, Om = _gpu(precision)
+    (c, g, h), F, T, Om = _gpu(precision)
     ref = oracle_ref
     tol = TOL[precision]
-    print(f"n={N} L={L} N_s={NS} {precision}: rel err F {abs(1 - c - ref['fidelity']) / ref['fidelity']:.2e} "
-          f"grad {_rel(g, ref['grad']):.2e} hvp {_rel(h, ref['hvp']):.2e}")
-    assert abs((1 - c) - ref["fidelity"]) <= tol * ref["fidelity"]
-    assert _rel(g, ref["grad"]) <= tol and _rel(h, ref["hvp"]) <= tol
+    eF = assert_fidelity(F, ref["fidelity"], tol, precision)
+    eg = assert_close(g, ref["grad"], tol, precision + " grad")
+    eh = assert_close(h, ref["hvp"], tol, precision + " hvp")
+    print(f"n={N} L={L} N_s={NS} {precision}: rel err F {eF:.2e} grad {eg[0]:.2e} (per gate {eg[1]:.2e}) "
+          f"hvp {eh[0]:.2e} (per gate {eh[1]:.2e})")
     assert np.linalg.norm(T - ref["T"]) <= tol * np.linalg.norm(ref["T"])
     # the same evaluation with the static split
     os.environ["QHVP_SCHEDULE"] = "static"
     try:
-        (c2, g2, h2), T2, Om2 = _gpu(precision)
+        (c2, g2, h2), F2, T2, Om2 = _gpu(precision)
     finally:
         del os.environ["QHVP_SCHEDULE"]
     assert c2 == c and np.array_equal(g2, g) and np.array_equal(h2, h)
