@@ -175,6 +175,27 @@ qhvp_status qhvp_forward_dev(qhvp_problem* p, const double* d_G, const double* d
                              double* d_cost, double* d_fidelity);
 qhvp_status qhvp_backward_dev(qhvp_problem* p, double* d_grad, double* d_hvp);
 
+/* ---- one HVP that allocates nothing ----
+ * For callers that cannot allocate memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  One HVP as qhvp_hvp_dev computes it, for a problem given in
+ * full on the device (U_ref gates, K_ref*16 complex FP64, and samples, n_samples*n*2 complex FP64, as
+ * for qhvp_problem_create; G, V and the outputs as for qhvp_hvp_dev), evaluated entirely inside a
+ * scratch area of QHVP_NOALLOC_SCRATCH_BYTES (64 MiB) of device memory that the library holds on
+ * each device from qhvp_ctx_create until the process ends.  The call allocates nothing (no device,
+ * pinned or torch memory, no events); it picks the fastest layer-checkpoint policy whose workspace
+ * fits the scratch, and returns QHVP_ERR_NOMEM before enqueueing anything if none does.  The labels
+ * are computed by every call.  Work is enqueued on hip_stream and the call returns without waiting.
+ * Every call on one device shares that device's scratch, which keeps the last call's contents (each
+ * call clears what it needs cleared): calls that overlap on one device - on different streams or
+ * from different threads - race, so serialise them (one stream).  d_cost, d_fidelity, d_grad may be
+ * NULL; values the device rejects leave the outputs untouched, as for qhvp_hvp_dev. */
+#define QHVP_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+qhvp_status qhvp_hvp_noalloc(qhvp_ctx* ctx, int n, int L, int L_ref, const double* d_uref_gates,
+                             const double* d_samples, int n_samples, qhvp_precision prec,
+                             const double* d_G, const double* d_V, qhvp_geometry geom,
+                             double* d_cost, double* d_fidelity, double* d_grad, double* d_hvp,
+                             void* hip_stream);
+
 /* Device-side input check of the last call (waits for the problem's stream): 0 if its inputs were
  * valid, else an OR of QHVP_DEV_NONFINITE and QHVP_DEV_NOT_UNITARY. */
 #define QHVP_DEV_NONFINITE 1    /* a non-finite entry in G or V */

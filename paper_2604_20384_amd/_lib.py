@@ -62,6 +62,8 @@ _SIGS = {
     "qhvp_forward_dev": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp, _vp]),
     "qhvp_backward_dev": (C.c_int, [_vp, _vp, _vp]),
     "qhvp_device_status": (C.c_int, [_vp, _ip]),
+    "qhvp_hvp_noalloc": (C.c_int, [_vp, C.c_int, C.c_int, C.c_int, _vp, _vp, C.c_int, C.c_int, _vp, _vp, C.c_int,
+                                   _vp, _vp, _vp, _vp, _vp]),
     "qhvp_hvp_batch": (C.c_int, [_vp, _dp, C.c_int, _dp, C.c_int, _dp, _dp, _dp]),
     "qhvp_states_kept_for": (C.c_int, [_vp, _dp]),
     "qhvp_forward": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp]),

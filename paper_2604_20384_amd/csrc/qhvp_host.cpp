@@ -857,7 +857,7 @@ qhvp_status core_forward(qhvp_problem* p, const double* d_G, const double* d_V, 
   p->fwd_ready = 0;
   p->ev_fwd = p->ev_bwd = 0;
   const int tangent = mode == 2 ? 1 : 0;
-  HIP_TRY(hipEventRecord(p->ev[0], p->stream));
+  if (p->ev[0]) HIP_TRY(hipEventRecord(p->ev[0], p->stream));
   qhvp::PrepArgs pa;
   std::memset(&pa, 0, sizeof(pa));
   pa.K = p->K;
@@ -883,8 +883,8 @@ qhvp_status core_forward(qhvp_problem* p, const double* d_G, const double* d_V, 
                                  mode == 0 ? 2 : 1);
   if (st) return st;
   if (mode != 0) p->invalidate_kept = 0;
-  HIP_TRY(hipEventRecord(p->ev[1], p->stream));
-  p->ev_fwd = 1;
+  if (p->ev[1]) HIP_TRY(hipEventRecord(p->ev[1], p->stream));
+  p->ev_fwd = p->ev[1] ? 1 : 0;
   p->have_eval = 1;
   p->last_tangent = tangent;
   if (mode != 0) {
@@ -925,15 +925,39 @@ qhvp_status core_backward(qhvp_problem* p, double* cost, double* fidelity, doubl
   HIP_TRY(hipSetDevice(p->ctx->device));
   if (!p->fwd_ready) return fail(QHVP_ERR_INVALID, "no forward sweep to differentiate (call qhvp_forward first)");
   p->fwd_ready = 0;
-  HIP_TRY(hipEventRecord(p->ev[2], p->stream));
+  if (p->ev[2]) HIP_TRY(hipEventRecord(p->ev[2], p->stream));
   qhvp_status st = backward_sweep(p, p->fwd_tangent);
   if (st) return st;
   const int mode = qhvp::kPostDeriv | ((cost || fidelity) ? qhvp::kPostCost : 0);
   st = core_post(p, mode, p->fwd_tangent, p->fwd_riem, cost, fidelity, grad, hvp);
   if (st) return st;
-  HIP_TRY(hipEventRecord(p->ev[3], p->stream));
-  p->ev_bwd = 1;
+  if (p->ev[3]) HIP_TRY(hipEventRecord(p->ev[3], p->stream));
+  p->ev_bwd = p->ev[3] ? 1 : 0;
   return QHVP_OK;
+}
+
+// A problem's host-side description (pass plans, checkpoint segments, workspace layout), with no
+// workspace, staging or events attached yet.
+qhvp_problem* new_problem(qhvp_ctx* ctx, int n, int L, int L_ref, int n_samples, qhvp_precision prec, int ckpt_every,
+                          int with_tangent, const Layout& lay, void* hip_stream) {
+  qhvp_problem* p = new qhvp_problem();
+  p->ctx = ctx;
+  p->n = n; p->L = L; p->L_ref = L_ref; p->Ns = n_samples;
+  p->K = num_gates(n, L); p->Kr = num_gates(n, L_ref);
+  p->prec = prec; p->ckpt_every = ckpt_every; p->tangent = with_tangent ? 1 : 0;
+  p->stream = (hipStream_t)hip_stream;
+  p->passes = plan_circuit(n, L, nullptr);
+  p->ref_passes = plan_circuit(n, L_ref, nullptr);
+  fill_tile_offsets(p->passes, (int)p->amp());
+  fill_tile_offsets(p->ref_passes, (int)p->amp());
+  p->seg = plan_segments(n, L, ckpt_every);
+  p->lay = lay;
+  p->ws = nullptr;
+  p->owns_ws = false;
+  p->h_in = nullptr;
+  p->h_out = p->h_tov = nullptr;
+  for (auto& e : p->ev) e = nullptr;
+  return p;
 }
 
 // ---- host calls: validated on the host, staged to the device, evaluated by the device path, and
@@ -1046,6 +1070,8 @@ qhvp_status qhvp_ctx_create(int device, qhvp_ctx** out) {
   HIP_TRY(hipGetDeviceCount(&cnt));
   if (device < 0 || device >= cnt) return fail(QHVP_ERR_INVALID, "no such HIP device");
   HIP_TRY(hipSetDevice(device));
+  // the scratch of qhvp_hvp_noalloc: its address on this device, looked up once
+  LAUNCH_TRY(qhvp::noalloc_scratch_init(device));
   *out = new qhvp_ctx{device};
   return QHVP_OK;
 }
@@ -1081,21 +1107,7 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
   if (d_workspace && ((uintptr_t)d_workspace % kAlign) != 0) return fail(QHVP_ERR_INVALID, "workspace must be 256-byte aligned");
   HIP_TRY(hipSetDevice(ctx->device));
 
-  qhvp_problem* p = new qhvp_problem();
-  p->ctx = ctx;
-  p->n = n; p->L = L; p->L_ref = L_ref; p->Ns = n_samples;
-  p->K = num_gates(n, L); p->Kr = Kr;
-  p->prec = prec; p->ckpt_every = ckpt_every; p->tangent = with_tangent ? 1 : 0;
-  p->stream = (hipStream_t)hip_stream;
-  p->passes = plan_circuit(n, L, nullptr);
-  p->ref_passes = plan_circuit(n, L_ref, nullptr);
-  fill_tile_offsets(p->passes, (int)p->amp());
-  fill_tile_offsets(p->ref_passes, (int)p->amp());
-  p->seg = plan_segments(n, L, ckpt_every);
-  p->lay = lay;
-  p->h_in = nullptr;
-  p->h_out = p->h_tov = nullptr;
-  for (auto& e : p->ev) e = nullptr;
+  qhvp_problem* p = new_problem(ctx, n, L, L_ref, n_samples, prec, ckpt_every, with_tangent, lay, hip_stream);
   auto cleanup_fail = [&](qhvp_status st, const std::string& msg) {
     qhvp_problem_destroy(p);
     return fail(st, msg);
@@ -1313,6 +1325,56 @@ qhvp_status qhvp_hvp_dev(qhvp_problem* p, const double* d_G, const double* d_V, 
   st = core_forward(p, d_G, d_V, geom == QHVP_RIEMANNIAN, 2);
   if (st) return st;
   return core_backward(p, d_cost, d_fidelity, d_grad, d_hvp);
+}
+
+qhvp_status qhvp_hvp_noalloc(qhvp_ctx* ctx, int n, int L, int L_ref, const double* d_uref_gates,
+                             const double* d_samples, int n_samples, qhvp_precision prec, const double* d_G,
+                             const double* d_V, qhvp_geometry geom, double* d_cost, double* d_fidelity,
+                             double* d_grad, double* d_hvp, void* hip_stream) {
+  if (!ctx) return fail(QHVP_ERR_INVALID, "ctx is NULL");
+  if (n < 2 || n > qhvp::kMaxQubits) return fail(QHVP_ERR_INVALID, "n must be in [2, 30]");
+  if (L < 1 || L_ref < 1) return fail(QHVP_ERR_INVALID, "L and L_ref must be >= 1");
+  if (n_samples < 1) return fail(QHVP_ERR_INVALID, "n_samples must be >= 1");
+  if (prec != QHVP_C128 && prec != QHVP_C64_ACC64) return fail(QHVP_ERR_INVALID, "unknown precision");
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  if (!d_V || !d_hvp) return fail(QHVP_ERR_INVALID, "V and hvp must not be NULL");
+  const int dev = ctx->device;
+  for (const double* ptr : {d_uref_gates, d_samples, d_G, d_V})
+    if (!device_pointer(ptr, dev)) return fail(QHVP_ERR_INVALID, "an input is not device memory of the context's device");
+  for (const double* ptr : {d_cost, d_fidelity, d_grad, d_hvp})
+    if (ptr && !device_pointer(ptr, dev)) return fail(QHVP_ERR_INVALID, "an output is not device memory of the context's device");
+  void* scratch = qhvp::noalloc_scratch(dev);
+  if (!scratch) return fail(QHVP_ERR_DEVICE, "no scratch on this device (qhvp_ctx_create did not finish)");
+  // the fastest checkpoint policy whose workspace fits the scratch
+  Layout lay;
+  int ckpt = 0;
+  bool fits = false;
+  for (int ck : {0, -2, 1, 2, 4, 8}) {
+    Layout l;
+    if (make_layout(n, L, L_ref, n_samples, prec, ck, 1, l) && l.total <= qhvp::kNoAllocScratchBytes) {
+      lay = l;
+      ckpt = ck;
+      fits = true;
+      break;
+    }
+  }
+  if (!fits)
+    return fail(QHVP_ERR_NOMEM, "the problem needs more than the " + std::to_string(qhvp::kNoAllocScratchBytes >> 20) +
+                                    " MiB of scratch of qhvp_hvp_noalloc (use qhvp_problem_create)");
+  HIP_TRY(hipSetDevice(dev));
+  qhvp_problem* p = new_problem(ctx, n, L, L_ref, n_samples, prec, ckpt, 1, lay, hip_stream);
+  p->ws = (char*)scratch;
+  // labels phi0 = U_ref psi (Alg. 2 takes them as input), then the HVP: all inside the scratch
+  qhvp_status st = QHVP_OK;
+  if (qhvp::launch_zero_ints(p->flags(), qhvp::kFlagCount, p->stream) != 0 ||
+      qhvp::launch_convert(d_samples, p->small(lay.o_samples), (long long)n_samples * n * 2, p->dprec(), p->stream) != 0 ||
+      qhvp::launch_convert(d_uref_gates, p->small(lay.o_uref), (long long)p->Kr * 16, p->dprec(), p->stream) != 0)
+    st = fail(QHVP_ERR_DEVICE, "launch failed while setting up the scratch");
+  if (st == QHVP_OK) st = forward_sweep(p, p->ref_passes, p->small(lay.o_uref), nullptr, 0, 0);
+  if (st == QHVP_OK) st = core_forward(p, d_G, d_V, geom == QHVP_RIEMANNIAN, 2);
+  if (st == QHVP_OK) st = core_backward(p, d_cost, d_fidelity, d_grad, d_hvp);
+  delete p;   // host-side description only: the scratch stays with the device
+  return st;
 }
 
 qhvp_status qhvp_device_status(qhvp_problem* p, int* status) {

@@ -172,5 +172,15 @@ struct PostArgs {
 };
 int launch_prep(const PrepArgs& a, void* stream);
 int launch_post(const PostArgs& a, void* stream);
+// dst = src (n_complex complex FP64 values, device) in the given precision.
+int launch_convert(const double* src, void* dst, long long n_complex, int prec, void* stream);
+
+// Scratch of the entry point that allocates nothing (a file-scope device array in qhvp_post.hip).
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+// Looks up the array's address on `device` (which must be current) once; returns a hipError_t.
+int noalloc_scratch_init(int device);
+// The array's address on `device` (null before noalloc_scratch_init succeeded there).
+void* noalloc_scratch(int device);
 
 }  // namespace qhvp

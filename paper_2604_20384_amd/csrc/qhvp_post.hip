@@ -6,12 +6,18 @@
 // one sum over samples: one workgroup, fixed summation orders, so results are bitwise repeatable.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <mutex>
+
 #include "qhvp_internal.h"
 
 namespace qhvp {
 namespace {
 
-constexpr int kPostThreads = 256;
+// Both kernels run one workgroup of kPostThreads threads; each thread keeps its 4x4 matrices in its
+// own slab of LDS (kSlab complex numbers), so that no kernel here uses private (scratch) memory.
+constexpr int kPostThreads = 32;
+constexpr int kSlab = 240;
 
 typedef double2 zd;
 __device__ __forceinline__ zd zmk(double x, double y) { return make_double2(x, y); }
@@ -26,7 +32,7 @@ __device__ __forceinline__ zd zdiv(zd a, zd b) {
   return zmk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
 }
 
-// 4x4 complex matrices, row-major: M[4 i + j]
+// 4x4 complex matrices, row-major: M[4 i + j]; c must not alias a or b
 __device__ void mm4(const zd* a, const zd* b, zd* c) {
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) {
@@ -39,47 +45,49 @@ __device__ void dag4(const zd* a, zd* b) {
   for (int i = 0; i < 4; ++i)
     for (int j = 0; j < 4; ++j) b[4 * i + j] = zconj(a[4 * j + i]);
 }
-// P_G(X) = X/2 - G X^dag G / 2, the projection onto the tangent space of U(4) at G (App. F)
-__device__ void project4(const zd* G, const zd* X, zd* out) {
-  zd Xd[16], t[16], u[16];
+// P_G(X) = X/2 - G X^dag G / 2, the projection onto the tangent space of U(4) at G (App. F).
+// tmp: 48 entries.
+__device__ void project4(const zd* G, const zd* X, zd* out, zd* tmp) {
+  zd *Xd = tmp, *t = tmp + 16, *u = tmp + 32;
   dag4(X, Xd);
   mm4(G, Xd, t);
   mm4(t, G, u);
   for (int i = 0; i < 16; ++i) out[i] = zsub(zscale(0.5, X[i]), zscale(0.5, u[i]));
 }
-// Riemannian HVP of App. F for a tangent direction V: P_G(H - V grad^dag G / 2 - G grad^dag V / 2)
-__device__ void riem_hvp4(const zd* G, const zd* gr, const zd* H, const zd* V, zd* out) {
-  zd grd[16], t1[16], t2[16], t3[16], t4[16], in[16];
+// Riemannian HVP of App. F for a tangent direction V: P_G(H - V grad^dag G / 2 - G grad^dag V / 2).
+// tmp: 144 entries.
+__device__ void riem_hvp4(const zd* G, const zd* gr, const zd* H, const zd* V, zd* out, zd* tmp) {
+  zd *grd = tmp, *t1 = tmp + 16, *t2 = tmp + 32, *t3 = tmp + 48, *t4 = tmp + 64, *in = tmp + 80;
   dag4(gr, grd);
   mm4(V, grd, t1);
   mm4(t1, G, t2);
   mm4(G, grd, t3);
   mm4(t3, V, t4);
   for (int i = 0; i < 16; ++i) in[i] = zsub(zsub(H[i], zscale(0.5, t2[i])), zscale(0.5, t4[i]));
-  project4(G, in, out);
+  project4(G, in, out, tmp + 96);
 }
-// Gauss-Jordan inverse with partial pivoting; false if a pivot vanishes.
-__device__ bool inv4(const zd* a, zd* out) {
-  zd m[4][8];
+// Gauss-Jordan inverse with partial pivoting; false if a pivot vanishes.  tmp: 32 entries (the
+// augmented matrix [a | I], row r at tmp[8 r]).
+__device__ bool inv4(const zd* a, zd* out, zd* m) {
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 8; ++j) m[i][j] = j < 4 ? a[4 * i + j] : zmk(j - 4 == i ? 1.0 : 0.0, 0.0);
+    for (int j = 0; j < 8; ++j) m[8 * i + j] = j < 4 ? a[4 * i + j] : zmk(j - 4 == i ? 1.0 : 0.0, 0.0);
   for (int c = 0; c < 4; ++c) {
     int piv = c;
     for (int r = c + 1; r < 4; ++r)
-      if (znorm(m[r][c]) > znorm(m[piv][c])) piv = r;
-    if (!(znorm(m[piv][c]) > 1e-300)) return false;
+      if (znorm(m[8 * r + c]) > znorm(m[8 * piv + c])) piv = r;
+    if (!(znorm(m[8 * piv + c]) > 1e-300)) return false;
     if (piv != c)
-      for (int j = 0; j < 8; ++j) { const zd t = m[c][j]; m[c][j] = m[piv][j]; m[piv][j] = t; }
-    const zd d = m[c][c];
-    for (int j = 0; j < 8; ++j) m[c][j] = zdiv(m[c][j], d);
+      for (int j = 0; j < 8; ++j) { const zd t = m[8 * c + j]; m[8 * c + j] = m[8 * piv + j]; m[8 * piv + j] = t; }
+    const zd d = m[8 * c + c];
+    for (int j = 0; j < 8; ++j) m[8 * c + j] = zdiv(m[8 * c + j], d);
     for (int r = 0; r < 4; ++r)
       if (r != c) {
-        const zd f = m[r][c];
-        for (int j = 0; j < 8; ++j) m[r][j] = zsub(m[r][j], zmul(f, m[c][j]));
+        const zd f = m[8 * r + c];
+        for (int j = 0; j < 8; ++j) m[8 * r + j] = zsub(m[8 * r + j], zmul(f, m[8 * c + j]));
       }
   }
   for (int i = 0; i < 4; ++i)
-    for (int j = 0; j < 4; ++j) out[4 * i + j] = m[i][j + 4];
+    for (int j = 0; j < 4; ++j) out[4 * i + j] = m[8 * i + j + 4];
   return true;
 }
 __device__ double fro4(const zd* a) {
@@ -87,8 +95,9 @@ __device__ double fro4(const zd* a) {
   for (int i = 0; i < 16; ++i) s += znorm(a[i]);
   return sqrt(s);
 }
-__device__ double unitarity_err4(const zd* G) {
-  zd Gd[16], P[16];
+// |G^dag G - I|_F; tmp: 32 entries
+__device__ double unitarity_err4(const zd* G, zd* tmp) {
+  zd *Gd = tmp, *P = tmp + 16;
   dag4(G, Gd);
   mm4(Gd, G, P);
   double e = 0;
@@ -118,12 +127,19 @@ __device__ void store_prec(const zd* m, void* dst, int prec) {
 }
 
 __global__ void __launch_bounds__(kPostThreads) k_prep(PrepArgs a) {
+  __shared__ zd slab[kPostThreads][kSlab];
+  __shared__ int sBad;
   const int tid = threadIdx.x;
+  zd* G = slab[tid];
+  zd* V = G + 16;
+  zd* Gi = G + 32;
+  zd* P = G + 48;
+  zd* tmp = G + 64;   // 48 (projection), 32 (inverse, unitarity), 32 (t, Y)
   const size_t amp = a.prec == P_C64 ? 8 : 16;
   int bad = 0, inv_ok = 1, same = 1;
+  if (tid == 0) sBad = 0;
   for (int k = tid; k < a.K; k += kPostThreads) {
     const double* gk = a.G_in + 32 * (size_t)k;
-    zd G[16], V[16], Gi[16];
     if (!finite16(gk)) bad |= kStatNonFinite;
     load4(gk, G);
     if (a.tangent) {
@@ -131,22 +147,21 @@ __global__ void __launch_bounds__(kPostThreads) k_prep(PrepArgs a) {
       if (!finite16(vk)) bad |= kStatNonFinite;
       load4(vk, V);
       if (a.riem) {
-        zd P[16];
-        project4(G, V, P);
+        project4(G, V, P, tmp);
         for (int i = 0; i < 16; ++i) V[i] = P[i];
       }
     } else {
       for (int i = 0; i < 16; ++i) V[i] = zmk(0, 0);
     }
-    if (a.riem && !(unitarity_err4(G) <= 1e-10)) bad |= kStatNotUnitary;
+    if (a.riem && !(unitarity_err4(G, tmp) <= 1e-10)) bad |= kStatNotUnitary;
     store_prec(G, (char*)a.gates + 16 * amp * (size_t)k, a.prec);
     if (a.tangent) store_prec(V, (char*)a.dirs + 16 * amp * (size_t)k, a.prec);
     store4(G, a.g64 + 32 * (size_t)k);
     store4(V, a.v64 + 32 * (size_t)k);
     if (a.with_inverse) {
-      const bool ok = inv4(G, Gi) && fro4(G) * fro4(Gi) <= kInverseCond;
+      const bool ok = inv4(G, Gi, tmp) && fro4(G) * fro4(Gi) <= kInverseCond;
       if (ok) {
-        zd t[16], Y[16];
+        zd *t = tmp + 32, *Y = tmp + 48;
         mm4(Gi, V, t);
         mm4(t, Gi, Y);
         for (int i = 0; i < 16; ++i) Y[i] = zscale(-1.0, Y[i]);
@@ -166,9 +181,6 @@ __global__ void __launch_bounds__(kPostThreads) k_prep(PrepArgs a) {
   const int any_bad = __syncthreads_or(bad);
   const int all_inv = __syncthreads_and(inv_ok);
   const int all_same = __syncthreads_and(same);
-  __shared__ int sBad;
-  if (tid == 0) sBad = 0;
-  __syncthreads();
   if (bad) atomicOr(&sBad, bad);
   __syncthreads();
   if (a.keep_mode) {
@@ -191,10 +203,11 @@ __global__ void __launch_bounds__(kPostThreads) k_prep(PrepArgs a) {
 // -(2/N_s) conj(Dhat) (the derivatives of the returned cost 1 - F).  Sums taken against pass-output
 // states (backward from pass outputs) are first mapped back: E = Et G^-T, D = (Dt - E V^T) G^-T.
 __global__ void __launch_bounds__(kPostThreads) k_post(PostArgs a) {
+  __shared__ zd slab[kPostThreads][kSlab];
+  __shared__ double red[kPostThreads];
   const int tid = threadIdx.x;
   if (a.flags[kFlagStatus] != 0) return;   // invalid inputs: every output is left as it was
   if (a.mode & kPostCost) {
-    __shared__ double red[kPostThreads];
     double f = 0;
     for (int s = tid; s < a.Ns; s += kPostThreads) f += a.tov[4 * s] * a.tov[4 * s] + a.tov[4 * s + 1] * a.tov[4 * s + 1];
     red[tid] = f;
@@ -212,15 +225,22 @@ __global__ void __launch_bounds__(kPostThreads) k_post(PostArgs a) {
   if (!(a.mode & kPostDeriv)) return;
   const bool mapped = a.flags[kFlagInverse] != 0;
   const double f = -2.0 / a.Ns;
+  zd* E = slab[tid];      // then the gradient, in place
+  zd* D = E + 16;         // then the HVP, in place
+  zd* gi = E + 32;
+  zd* v = E + 48;
+  zd* Et = E + 64;
+  zd* W = E + 80;
+  zd* G = E + 32;         // Riemannian outputs (after the mapping is done with gi)
+  zd* out = E + 64;
+  zd* tmp = E + 96;       // 144
   for (int k = tid; k < a.K; k += kPostThreads) {
     const double* e = a.env + (size_t)k * kEnvVals;
-    zd E[16], D[16], gr[16], H[16];
     for (int i = 0; i < 16; ++i) {
       E[i] = zmk(e[2 * i], e[2 * i + 1]);
       D[i] = zmk(e[32 + 2 * i], e[32 + 2 * i + 1]);
     }
     if (mapped) {
-      zd gi[16], v[16], Et[16], W[16];
       load4(a.gi64 + 32 * (size_t)k, gi);
       load4(a.v64 + 32 * (size_t)k, v);
       for (int i = 0; i < 16; ++i) Et[i] = E[i];
@@ -245,30 +265,68 @@ __global__ void __launch_bounds__(kPostThreads) k_post(PostArgs a) {
         }
     }
     for (int i = 0; i < 16; ++i) {
-      gr[i] = zmk(f * E[i].x, -f * E[i].y);
-      H[i] = zmk(f * D[i].x, -f * D[i].y);
+      E[i] = zmk(f * E[i].x, -f * E[i].y);
+      D[i] = zmk(f * D[i].x, -f * D[i].y);
     }
     if (a.riem) {
-      zd G[16], out[16];
       load4(a.g64 + 32 * (size_t)k, G);
       if (a.grad) {
-        project4(G, gr, out);
+        project4(G, E, out, tmp);
         store4(out, a.grad + 32 * (size_t)k);
       }
       if (a.hvp && a.tangent) {
-        zd v[16];
         load4(a.v64 + 32 * (size_t)k, v);
-        riem_hvp4(G, gr, H, v, out);
+        riem_hvp4(G, E, D, v, out, tmp);
         store4(out, a.hvp + 32 * (size_t)k);
       }
     } else {
-      if (a.grad) store4(gr, a.grad + 32 * (size_t)k);
-      if (a.hvp && a.tangent) store4(H, a.hvp + 32 * (size_t)k);
+      if (a.grad) store4(E, a.grad + 32 * (size_t)k);
+      if (a.hvp && a.tangent) store4(D, a.hvp + 32 * (size_t)k);
     }
   }
 }
 
+__global__ void k_convert(const double* __restrict__ src, void* dst, long long n_complex, int prec) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n_complex;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (prec == P_C64) ((float2*)dst)[i] = make_float2((float)src[2 * i], (float)src[2 * i + 1]);
+    else ((double2*)dst)[i] = make_double2(src[2 * i], src[2 * i + 1]);
+  }
+}
+
+// The scratch of the entry point that allocates nothing: every problem evaluated through it lives
+// here (labels, states, partial sums, flags).  Each device that loads the library holds its own copy
+// of this array until the process ends; host code uses only the address looked up per device below,
+// never the array's name.
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
 }  // namespace
+
+int noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return (int)hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[device]) return (int)hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return (int)e;
+  g_scratch[device] = ptr;
+  return (int)hipSuccess;
+}
+
+void* noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[device];
+}
+
+int launch_convert(const double* src, void* dst, long long n_complex, int prec, void* stream) {
+  if (n_complex <= 0) return (int)hipSuccess;
+  const long long blocks = std::min<long long>((n_complex + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_convert, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, src, dst, n_complex, prec);
+  return (int)hipGetLastError();
+}
 
 int launch_prep(const PrepArgs& a, void* stream) {
   hipLaunchKernelGGL(k_prep, dim3(1), dim3(kPostThreads), 0, (hipStream_t)stream, a);
