@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -529,7 +530,15 @@ bool polar4(const cd* A, cd* U) {
 
 // --------------------------------------------------------------------------------------------
 struct qhvp_ctx {
+  explicit qhvp_ctx(int d) : device(d) {}
   int device;
+  // Pinned host buffers and events of destroyed problems, handed to later problems of this context
+  // (a serving slot creates one problem per request), so that creating a problem does not pin host
+  // memory or create events each time.  At most kPoolKeep of each are kept.
+  static constexpr size_t kPoolKeep = 16;
+  std::mutex mu;
+  std::vector<std::pair<size_t, void*>> pinned;   // (bytes, pointer)
+  std::vector<hipEvent_t> events;
 };
 
 struct qhvp_problem {
@@ -548,6 +557,7 @@ struct qhvp_problem {
   void* h_in;
   double* h_out;
   double* h_tov;
+  size_t h_in_bytes = 0, h_out_bytes = 0, h_tov_bytes = 0;
   // two-phase evaluation: a forward sweep leaves its checkpoints for one backward sweep
   int fwd_ready = 0, fwd_tangent = 0, fwd_riem = 0;
   int last_tangent = 0, have_eval = 0;
@@ -936,6 +946,63 @@ qhvp_status core_backward(qhvp_problem* p, double* cost, double* fidelity, doubl
   return QHVP_OK;
 }
 
+// The context's pools (thread-safe): the smallest pooled buffer of at least `bytes`, else a new one;
+// *got receives its size.
+void* pool_pinned(qhvp_ctx* c, size_t bytes, size_t* got) {
+  *got = bytes;
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    size_t best = c->pinned.size();
+    for (size_t i = 0; i < c->pinned.size(); ++i)
+      if (c->pinned[i].first >= bytes && (best == c->pinned.size() || c->pinned[i].first < c->pinned[best].first)) best = i;
+    if (best < c->pinned.size()) {
+      void* ptr = c->pinned[best].second;
+      *got = c->pinned[best].first;
+      c->pinned.erase(c->pinned.begin() + best);
+      return ptr;
+    }
+  }
+  void* ptr = nullptr;
+  if (hipHostMalloc(&ptr, bytes) != hipSuccess) return nullptr;
+  return ptr;
+}
+// Returns a buffer (its true size: a pooled buffer may be larger than its problem asked for).
+void pool_release_pinned(qhvp_ctx* c, void* ptr, size_t bytes) {
+  if (!ptr) return;
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (c->pinned.size() < qhvp_ctx::kPoolKeep) {
+      c->pinned.emplace_back(bytes, ptr);
+      return;
+    }
+  }
+  hipHostFree(ptr);
+}
+hipEvent_t pool_event(qhvp_ctx* c) {
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (!c->events.empty()) {
+      hipEvent_t e = c->events.back();
+      c->events.pop_back();
+      return e;
+    }
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+void pool_release_event(qhvp_ctx* c, hipEvent_t e) {
+  if (!e) return;
+  {
+    std::lock_guard<std::mutex> lock(c->mu);
+    if (c->events.size() < 4 * qhvp_ctx::kPoolKeep) {
+      c->events.push_back(e);
+      return;
+    }
+  }
+  hipEventDestroy(e);
+}
+
 // A problem's host-side description (pass plans, checkpoint segments, workspace layout), with no
 // workspace, staging or events attached yet.
 qhvp_problem* new_problem(qhvp_ctx* ctx, int n, int L, int L_ref, int n_samples, qhvp_precision prec, int ckpt_every,
@@ -1072,11 +1139,16 @@ qhvp_status qhvp_ctx_create(int device, qhvp_ctx** out) {
   HIP_TRY(hipSetDevice(device));
   // the scratch of qhvp_hvp_noalloc: its address on this device, looked up once
   LAUNCH_TRY(qhvp::noalloc_scratch_init(device));
-  *out = new qhvp_ctx{device};
+  *out = new qhvp_ctx(device);
   return QHVP_OK;
 }
 
-void qhvp_ctx_destroy(qhvp_ctx* ctx) { delete ctx; }
+void qhvp_ctx_destroy(qhvp_ctx* ctx) {
+  if (!ctx) return;
+  for (auto& b : ctx->pinned) hipHostFree(b.second);
+  for (auto e : ctx->events) hipEventDestroy(e);
+  delete ctx;
+}
 
 size_t qhvp_workspace_bytes(int n, int L, int L_ref, int n_samples, qhvp_precision prec, int ckpt_every,
                             int with_tangent) {
@@ -1123,12 +1195,14 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
   }
   const size_t amp = p->amp();
   const size_t in_bytes = std::max({(size_t)p->K * 64 * sizeof(double), (size_t)Kr * 16 * amp, (size_t)n_samples * n * 2 * amp});
-  if (hipHostMalloc(&p->h_in, in_bytes) != hipSuccess ||
-      hipHostMalloc((void**)&p->h_out, (2 + (size_t)p->K * 64) * sizeof(double)) != hipSuccess ||
-      hipHostMalloc((void**)&p->h_tov, std::max((size_t)n_samples * 4, (size_t)qhvp::kFlagCount) * sizeof(double)) != hipSuccess)
+  const size_t out_bytes = (2 + (size_t)p->K * 64) * sizeof(double);
+  const size_t tov_bytes = std::max((size_t)n_samples * 4, (size_t)qhvp::kFlagCount) * sizeof(double);
+  if (!(p->h_in = pool_pinned(ctx, in_bytes, &p->h_in_bytes)) ||
+      !(p->h_out = (double*)pool_pinned(ctx, out_bytes, &p->h_out_bytes)) ||
+      !(p->h_tov = (double*)pool_pinned(ctx, tov_bytes, &p->h_tov_bytes)))
     return cleanup_fail(QHVP_ERR_NOMEM, "pinned host allocation failed");
   for (auto& e : p->ev)
-    if (hipEventCreate(&e) != hipSuccess) return cleanup_fail(QHVP_ERR_DEVICE, "hipEventCreate failed");
+    if (!(e = pool_event(ctx))) return cleanup_fail(QHVP_ERR_DEVICE, "hipEventCreate failed");
 
   // per-call flags start cleared (no kept states); samples and U_ref gates to the device, then the
   // labels phi0 = U_ref psi (a forward sweep of U_ref)
@@ -1153,11 +1227,10 @@ void qhvp_problem_destroy(qhvp_problem* p) {
   if (p->stream) hipStreamSynchronize(p->stream);
   else hipDeviceSynchronize();
   if (p->owns_ws && p->ws) hipFree(p->ws);
-  if (p->h_in) hipHostFree(p->h_in);
-  if (p->h_out) hipHostFree(p->h_out);
-  if (p->h_tov) hipHostFree(p->h_tov);
-  for (auto e : p->ev)
-    if (e) hipEventDestroy(e);
+  pool_release_pinned(p->ctx, p->h_in, p->h_in_bytes);
+  pool_release_pinned(p->ctx, p->h_out, p->h_out_bytes);
+  pool_release_pinned(p->ctx, p->h_tov, p->h_tov_bytes);
+  for (auto e : p->ev) pool_release_event(p->ctx, e);
   for (auto e : p->evpool) hipEventDestroy(e);
   delete p;
 }

@@ -11,7 +11,8 @@ samples, Sec. IV).  A request's result therefore does not depend on what else is
 kernels reduce in a fixed order, so it is bitwise the same alone and in the mix.
 
 Latency = completion time - arrival time (including the request's label sweep
-phi_s = U_ref psi_s, which every new request needs).
+phi_s = U_ref psi_s, which every new request needs).  A queued request can be cancelled through its
+future (Future.cancel) until a slot takes it; the others are not held up.
 """
 from __future__ import annotations
 
@@ -171,9 +172,10 @@ class GpuExecutor:
                 else:
                     c, g = p.grad(req.G)
                     h = None
+                F = p.last_fidelity       # as computed (1 - c cancels when F is small)
             finally:
                 p.close()
-        return 1.0 - c, g, h
+        return F, g, h
 
 
 class Server:
@@ -191,6 +193,7 @@ class Server:
         self._next_id = 0
         self.results: list[Result] = []
         self.busy_s = 0.0
+        self.cancelled = 0
         self._threads = []
         for i in range(slots):
             t = threading.Thread(target=self._worker, args=(i,), daemon=True)
@@ -209,11 +212,15 @@ class Server:
         return fut
 
     def _take(self):
-        """FIFO head, once its memory fits (head-of-line blocking keeps the order fair)."""
+        """FIFO head, once its memory fits (head-of-line blocking keeps the order fair).  Cancelled
+        requests are dropped when they reach the head, before any memory is taken for them."""
         with self._cv:
             while True:
                 if self._stop and not self._q:
                     return None
+                while self._q and self._q[0][2].cancelled():
+                    self._q.popleft()
+                    self.cancelled += 1
                 if self._q:
                     nbytes = self._q[0][1].bytes
                     if self.arena is not None:
@@ -240,6 +247,11 @@ class Server:
             if item is None:
                 return
             req, plan, fut, off = item
+            if not fut.set_running_or_notify_cancel():     # cancelled after it was taken
+                with self._cv:
+                    self.cancelled += 1
+                self._release(plan.bytes, off)
+                continue
             ws = None if off is None else (self.arena.base + off, plan.bytes)
             t0 = time.perf_counter()
             try:
@@ -278,6 +290,24 @@ class Server:
             self.arena = None          # release the device buffer
 
 
+def busy_fraction(results, t_start: float, t_end: float) -> float:
+    """Share of [t_start, t_end] during which at least one request was running (the union of the
+    requests' start..end intervals; each request keeps the device working from start to end)."""
+    spans = sorted((r.start, r.end) for r in results)
+    busy, cur_s, cur_e = 0.0, None, None
+    for s0, e0 in spans:
+        s0, e0 = max(s0, t_start), min(e0, t_end)
+        if cur_e is None or s0 > cur_e:
+            if cur_e is not None:
+                busy += cur_e - cur_s
+            cur_s, cur_e = s0, e0
+        else:
+            cur_e = max(cur_e, e0)
+    if cur_e is not None:
+        busy += cur_e - cur_s
+    return busy / max(1e-9, t_end - t_start)
+
+
 def latency_report(results, t_start: float, t_end: float) -> dict:
     lat = np.array([r.latency for r in results])
     return {
@@ -286,6 +316,7 @@ def latency_report(results, t_start: float, t_end: float) -> dict:
         "p50_s": float(np.percentile(lat, 50)) if len(lat) else None,
         "p99_s": float(np.percentile(lat, 99)) if len(lat) else None,
         "mean_s": float(lat.mean()) if len(lat) else None,
+        "busy_frac": busy_fraction(results, t_start, t_end) if len(lat) else None,
     }
 
 

@@ -119,6 +119,29 @@ def test_oversized_request_is_rejected():
     srv.shutdown()
 
 
+def test_cancel_a_queued_request():
+    """A request cancelled while queued is dropped when it reaches the head, without taking memory
+    or a slot; the requests around it are served."""
+    ex = FakeExecutor(delay=0.05)
+    srv = serve.Server(ex, slots=1, memory_budget=1 << 40)
+    futs = [srv.submit(_req(4, 2, 2, "grad", i)) for i in range(4)]
+    time.sleep(0.01)                                  # the first one is running by now
+    assert futs[2].cancel()
+    assert not futs[0].cancel()                       # a running request cannot be cancelled
+    done = [futs[i].result() for i in (0, 1, 3)]
+    srv.shutdown()
+    assert futs[2].cancelled() and srv.cancelled == 1
+    assert [r.rid for r in done] == [0, 1, 3] and 2 not in ex.order
+    assert srv._free == 1 << 40                      # nothing held: the cancelled one never took memory
+
+
+def test_busy_fraction():
+    R = serve.Result
+    res = [R(0, 0, 0, None, None, 0.0, 1.0, 3.0, None), R(1, 0, 0, None, None, 0.0, 2.0, 4.0, None),
+           R(2, 0, 0, None, None, 0.0, 6.0, 7.0, None)]
+    assert abs(serve.busy_fraction(res, 0.0, 10.0) - 0.4) < 1e-12
+
+
 def test_latency_report_and_poisson():
     rng = np.random.default_rng(0)
     arr = serve.poisson_arrivals(rng, rate=50.0, count=2000)
@@ -152,6 +175,28 @@ def test_gpu_results_alone_equal_results_in_the_mix(gpu):
     rep = serve.latency_report(res, t0, t1)
     print("served:", rep)
     assert rep["requests"] == 16
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision,tol", [("c128", 1e-10), ("c64", 1e-5)])
+def test_gpu_chunked_request_against_oracle(gpu, precision, tol):
+    """A request whose workspace exceeds the per-request cap is split into sample chunks on the GPU;
+    the sample-weighted sum of the chunks' results equals the oracle over all samples."""
+    from parity import assert_close, assert_fidelity
+    from paper_2604_20384_amd.api import workspace_bytes
+    p = make_problem(10, 4, 9, seed=91)
+    q = serve.Request("hvp", 10, 4, p.uref, p.samples, p.G, p.V, L_ref=p.L_ref, precision=precision)
+    cap = workspace_bytes(10, 4, 8, 3, precision, 0, True)
+    plan = serve.plan_request(q, workspace_bytes, cap)
+    assert len(plan.chunks) >= 3, plan
+    srv = serve.Server(serve.GpuExecutor(), slots=2, memory_budget=4 * cap, request_cap=cap)
+    r = srv.submit(q).result()
+    srv.shutdown()
+    psi, phi = circuit.labels(p.uref, p.samples, p.n, p.L_ref)
+    ref = sv.evaluate(psi, phi, p.G, p.V, p.n, p.L)
+    assert_fidelity(r.fidelity, ref["fidelity"], tol, "chunked")
+    assert_close(r.grad, ref["grad"], tol, "chunked grad")
+    assert_close(r.hvp, ref["hvp"], tol, "chunked hvp")
 
 
 def test_arena_first_fit_and_coalescing():
