@@ -10,6 +10,7 @@ input) and reported separately as setup time.  Further legs, reported beside the
 * fixed_G: HVPs along several directions at one G (the forward states at G are kept between calls);
 * ckpt4: the headline workload with layer checkpointing every 4 layers (rate and peak HBM);
 * c128: the same workload in complex128, with its own roofline against the FP64 peak;
+* ti: the translationally invariant ansatz (one gate per layer, per-layer outputs, App. E);
 * accuracy: fidelity, gradient and HVP errors against the oracle on samples 0-3 (both precisions)
   and complex64 against complex128 on all 256 samples, globally and gate by gate;
 * serving: a Poisson stream of mixed gradient / HVP requests (n 10-22, L 4-32, N_s 16-256,
@@ -55,7 +56,7 @@ def parse():
                     help="only run a 2 GiB device copy 5 times (calibrates HBM traffic counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle runs (and the accuracy leg)")
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--no-legs", action="store_true", help="skip the ckpt4 and c128 legs")
+    ap.add_argument("--no-legs", action="store_true", help="skip the accuracy, ckpt4, ti and c128 legs")
     ap.add_argument("--serve-requests", type=int, default=40, help="requests per arrival rate")
     ap.add_argument("--serve-rates", default="0.25,0.5,0.75,0.9,1.0,1.2",
                     help="arrival rates as multiples of the measured serial capacity")
@@ -285,6 +286,36 @@ def leg(prob, precision, ckpt, steps, rng_seed):
     return out
 
 
+def ti_leg(prob, steps, rng_seed, headline_hvps):
+    """Translationally invariant ansatz (App. E) at the headline setting: one Haar gate and one
+    tangent direction per layer, from-scratch HVP calls with per-layer outputs.  The layer gates
+    are expanded and the per-layer sums taken on the device, so the rate should equal the
+    headline rate."""
+    import numpy as np
+    import torch
+
+    from paper_2604_20384_amd.api import Problem
+    from paper_2604_20384_amd.inputs import haar_unitary, random_tangent
+    rng = np.random.default_rng(rng_seed)
+    Gs = [haar_unitary(rng, 4, prob.L) for _ in range(steps + 1)]
+    Vs = [random_tangent(rng, G) for G in Gs]
+    torch.cuda.empty_cache()
+    gp = Problem(prob.n, prob.L, prob.uref, prob.samples, L_ref=prob.L_ref, precision="c64", ckpt_every=0,
+                 device=0)
+    gp.hvp_ti(Gs[0], Vs[0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(1, steps + 1):
+        gp.hvp_ti(Gs[i], Vs[i])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    gp.close()
+    return {"value": round(steps / dt, 4), "unit": "HVP/s", "ms_per_hvp": round(1e3 * dt / steps, 3),
+            "steps": steps, "precision": "c64", "ckpt_every_layers": 0,
+            "vs_headline": round(steps / dt / headline_hvps, 4),
+            "note": f"{prob.L} layer gates, per-layer gradient and HVP (App. E)"}
+
+
 def serving_sweep(n_req, rate_factors, seed):
     """Poisson streams of mixed gradient / HVP requests (complex64; n 10-22, L 4-32, N_s 16-256),
     at rates swept as multiples of the measured serial capacity mu: each rate's stream served one
@@ -411,6 +442,7 @@ def main():
         acc_gpu["c64_4"] = one_hvp(prob, "c64", 0, ns=ORACLE_SAMPLES)
         acc_gpu["c128_4"] = one_hvp(prob, "c128", 0, ns=ORACLE_SAMPLES)
         out["ckpt4"] = leg(prob, "c64", 4, 5, args.seed + 2000)
+        out["ti"] = ti_leg(prob, 5, args.seed + 4000, hvps)
         ck128 = pick_ckpt(n, L, prob.L_ref, ns, "c128")
         out["c128"] = leg(prob, "c128", ck128, 4, args.seed + 3000)
         acc_gpu["c128_full"] = one_hvp(prob, "c128", ck128)

@@ -230,14 +230,28 @@ qhvp_status qhvp_forward(qhvp_problem* p, const double* G, const double* V, qhvp
 qhvp_status qhvp_backward(qhvp_problem* p, double* grad, double* hvp);
 
 /* Translationally invariant brickwalls (App. E, Alg. 3): every gate of layer l is the same
- * G_(l).  G_layers, V_layers, grad_layers, hvp_layers hold L*16 complex (one 4x4 per layer).
- * The gradient and HVP with respect to G_(l) are the sums over the layer's gates of the per-gate
- * ones, with the direction V_(l) on every gate of layer l; Riemannian outputs are projected at
- * G_(l) (App. F on U(4)^L, V projected first).  `grad_layers` may be NULL in qhvp_hvp_ti. */
+ * G_(l).  G_layers, V_layers, grad_layers, hvp_layers hold L*16 complex (one 4x4 per layer,
+ * row-major, interleaved re/im doubles; host memory, owned by the caller).  The gradient and HVP
+ * with respect to G_(l) are the sums over the layer's gates of the per-gate ones, with the
+ * direction V_(l) on every gate of layer l (a layer without gates, e.g. the odd layers at n = 2,
+ * gives zero); Riemannian outputs are projected at G_(l) (App. F on U(4)^L, V projected first).
+ * The layer gates are expanded and the per-layer sums taken on the device (FP64, gates added in
+ * increasing order), so the cost of a call is that of qhvp_grad / qhvp_hvp on the expanded
+ * circuit.  cost, fidelity and grad_layers may be NULL in qhvp_hvp_ti (grad_layers is required in
+ * qhvp_grad_ti).  Errors as for qhvp_grad / qhvp_hvp: every output is left untouched. */
 qhvp_status qhvp_grad_ti(qhvp_problem* p, const double* G_layers, qhvp_geometry geom, double* cost,
-                         double* grad_layers);
+                         double* fidelity, double* grad_layers);
 qhvp_status qhvp_hvp_ti(qhvp_problem* p, const double* G_layers, const double* V_layers, qhvp_geometry geom,
-                        double* cost, double* grad_layers, double* hvp_layers);
+                        double* cost, double* fidelity, double* grad_layers, double* hvp_layers);
+/* Device-pointer forms of the two calls above (App. E): every array and scalar is device memory of
+ * the problem's device, L*16 complex per array; the work is enqueued on the problem's stream and
+ * the call returns without waiting.  Inputs found invalid on the device (non-finite entries, or
+ * non-unitary layer gates in Riemannian geometry) leave every output untouched and are reported by
+ * qhvp_device_status. */
+qhvp_status qhvp_grad_ti_dev(qhvp_problem* p, const double* d_G_layers, qhvp_geometry geom, double* d_cost,
+                             double* d_fidelity, double* d_grad_layers);
+qhvp_status qhvp_hvp_ti_dev(qhvp_problem* p, const double* d_G_layers, const double* d_V_layers, qhvp_geometry geom,
+                            double* d_cost, double* d_fidelity, double* d_grad_layers, double* d_hvp_layers);
 
 /* Per-sample overlaps T_s and Omega_s = D(T_s)[V] (n_samples complex each, host) of
  * the last cost/grad/hvp call (Omega is zero unless that call was an HVP). */

@@ -68,8 +68,10 @@ _SIGS = {
     "qhvp_states_kept_for": (C.c_int, [_vp, _dp]),
     "qhvp_forward": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp]),
     "qhvp_backward": (C.c_int, [_vp, _dp, _dp]),
-    "qhvp_grad_ti": (C.c_int, [_vp, _dp, C.c_int, _dp, _dp]),
-    "qhvp_hvp_ti": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp, _dp]),
+    "qhvp_grad_ti": (C.c_int, [_vp, _dp, C.c_int, _dp, _dp, _dp]),
+    "qhvp_hvp_ti": (C.c_int, [_vp, _dp, _dp, C.c_int, _dp, _dp, _dp, _dp]),
+    "qhvp_grad_ti_dev": (C.c_int, [_vp, _vp, C.c_int, _vp, _vp, _vp]),
+    "qhvp_hvp_ti_dev": (C.c_int, [_vp, _vp, _vp, C.c_int, _vp, _vp, _vp, _vp]),
     "qhvp_overlaps": (C.c_int, [_vp, _dp, _dp]),
     "qhvp_problem_info": (C.c_int, [_vp, _ip, _ip, _szp, _ip]),
     "qhvp_last_device_ms": (C.c_double, [_vp]),

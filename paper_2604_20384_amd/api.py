@@ -175,19 +175,21 @@ class Problem:
         return c.value, g, h
 
     # ---- device-pointer calls on torch tensors (complex128, shape (K, 4, 4), on the problem's device)
-    def _dev_in(self, t, name):
+    def _dev_in(self, t, name, count=None):
         import torch
-        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or t.shape != (self.K, 4, 4):
-            raise ValueError(f"{name} must be a complex128 torch tensor of shape ({self.K}, 4, 4)")
+        count = self.K if count is None else count
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or t.shape != (count, 4, 4):
+            raise ValueError(f"{name} must be a complex128 torch tensor of shape ({count}, 4, 4)")
         if t.device != torch.device(f"cuda:{self.device}"):
             raise ValueError(f"{name} must be on cuda:{self.device}")
         return t.contiguous()
 
-    def _dev_out(self, n_mats):
+    def _dev_out(self, n_mats, count=None):
         import torch
         dev = f"cuda:{self.device}"
+        count = self.K if count is None else count
         scal = torch.empty(2, dtype=torch.float64, device=dev)
-        mats = [torch.empty((self.K, 4, 4), dtype=torch.complex128, device=dev) for _ in range(n_mats)]
+        mats = [torch.empty((count, 4, 4), dtype=torch.complex128, device=dev) for _ in range(n_mats)]
         return scal, mats
 
     def cost_dev(self, G):
@@ -291,13 +293,14 @@ class Problem:
         check(lib.qhvp_backward(self.handle, dptr(_f64(g)), None if h is None else dptr(_f64(h))))
         return g if h is None else (g, h)
 
-    # ---- translationally invariant circuits: one (4, 4) gate per layer
+    # ---- translationally invariant circuits (App. E): one (4, 4) gate per layer, shape (L, 4, 4)
     def grad_ti(self, G_layers, riemannian=False):
         self.epoch += 1
         G = _c128(G_layers, (self.L, 4, 4))
         g = np.empty((self.L, 4, 4), dtype=np.complex128)
-        c = C.c_double()
-        check(lib.qhvp_grad_ti(self.handle, dptr(_f64(G)), int(riemannian), C.byref(c), dptr(_f64(g))))
+        c, f = C.c_double(), C.c_double()
+        check(lib.qhvp_grad_ti(self.handle, dptr(_f64(G)), int(riemannian), C.byref(c), C.byref(f), dptr(_f64(g))))
+        self.last_fidelity = f.value
         return c.value, g
 
     def hvp_ti(self, G_layers, V_layers, riemannian=False):
@@ -306,10 +309,31 @@ class Problem:
         V = _c128(V_layers, (self.L, 4, 4))
         g = np.empty((self.L, 4, 4), dtype=np.complex128)
         h = np.empty((self.L, 4, 4), dtype=np.complex128)
-        c = C.c_double()
-        check(lib.qhvp_hvp_ti(self.handle, dptr(_f64(G)), dptr(_f64(V)), int(riemannian), C.byref(c),
+        c, f = C.c_double(), C.c_double()
+        check(lib.qhvp_hvp_ti(self.handle, dptr(_f64(G)), dptr(_f64(V)), int(riemannian), C.byref(c), C.byref(f),
                               dptr(_f64(g)), dptr(_f64(h))))
+        self.last_fidelity = f.value
         return c.value, g, h
+
+    def grad_ti_dev(self, G_layers, riemannian=False):
+        """(cost, fidelity, per-layer gradient) as device tensors; G_layers (L, 4, 4) on the device."""
+        self.epoch += 1
+        G = self._dev_in(G_layers, "G_layers", self.L)
+        scal, (g,) = self._dev_out(1, self.L)
+        check(lib.qhvp_grad_ti_dev(self.handle, G.data_ptr(), int(riemannian), scal.data_ptr(), scal.data_ptr() + 8,
+                                   g.data_ptr()))
+        self._dev_keep = (G,)
+        return scal[0], scal[1], g
+
+    def hvp_ti_dev(self, G_layers, V_layers, riemannian=False):
+        """(cost, fidelity, per-layer gradient, per-layer HVP along V_layers) as device tensors."""
+        self.epoch += 1
+        G, V = self._dev_in(G_layers, "G_layers", self.L), self._dev_in(V_layers, "V_layers", self.L)
+        scal, (g, h) = self._dev_out(2, self.L)
+        check(lib.qhvp_hvp_ti_dev(self.handle, G.data_ptr(), V.data_ptr(), int(riemannian), scal.data_ptr(),
+                                  scal.data_ptr() + 8, g.data_ptr(), h.data_ptr()))
+        self._dev_keep = (G, V)
+        return scal[0], scal[1], g, h
 
     def overlaps(self):
         T = np.empty(self.n_samples, dtype=np.complex128)

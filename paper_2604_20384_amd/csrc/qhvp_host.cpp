@@ -381,8 +381,10 @@ struct Layout {
   size_t o_samples, o_gates, o_dirs, o_igates, o_uref, o_tov, o_ovpart, o_envpart, o_env, o_sched;
   // per-call FP64 buffers: the call's G and V as given (host calls stage them here), the FP64 copies
   // the post-processing reads (G, the possibly projected V, G^-1), the gates the kept pass-boundary
-  // states belong to, the per-call flags and the outputs of host calls (cost, fidelity, grad, hvp)
-  size_t o_gin, o_vin, o_g64, o_v64, o_gi64, o_keptg, o_flags, o_out;
+  // states belong to, the per-call flags and the outputs of host calls (cost, fidelity, grad, hvp);
+  // for translationally invariant calls the layer gates and directions as given and the per-layer
+  // gradient and HVP
+  size_t o_gin, o_vin, o_g64, o_v64, o_gi64, o_keptg, o_flags, o_out, o_tiin, o_tiout;
 };
 
 // Tile-schedule counters (one int per launch, zeroed at the start of every sweep)
@@ -429,6 +431,9 @@ bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_
   lay.o_keptg = o;   o = align_up(o + g64);
   lay.o_flags = o;   o = align_up(o + qhvp::kFlagCount * sizeof(int));
   lay.o_out = o;     o = align_up(o + 2 * sizeof(double) + 2 * g64);
+  const size_t l64 = (size_t)L * 32 * sizeof(double);
+  lay.o_tiin = o;    o = align_up(o + 2 * l64);
+  lay.o_tiout = o;   o = align_up(o + 2 * l64);
   lay.total = lay.off_small + o;
   return true;
 }
@@ -1068,11 +1073,13 @@ double* out_cost(qhvp_problem* p) { return p->dbuf(p->lay.o_out); }
 double* out_grad(qhvp_problem* p) { return p->dbuf(p->lay.o_out) + 2; }
 double* out_hvp(qhvp_problem* p) { return p->dbuf(p->lay.o_out) + 2 + (size_t)p->K * 32; }
 
-// Brings the staged outputs back, waits, and (only then) writes the caller's outputs.
-qhvp_status finish_host_call(qhvp_problem* p, double* cost, double* fidelity, double* grad, double* hvp) {
-  const size_t gn = (size_t)p->K * 32;
-  const size_t cnt = 2 + ((grad || hvp) ? (hvp ? 2 * gn : gn) : 0);
-  HIP_TRY(hipMemcpyAsync(p->h_out, out_cost(p), cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+// Brings the staged outputs back (cost and fidelity; the gradient, then the HVP, `gn` doubles each,
+// contiguous from `src`), waits, and (only then) writes the caller's outputs.
+qhvp_status finish_host_call(qhvp_problem* p, const double* src, size_t gn, double* cost, double* fidelity, double* grad,
+                             double* hvp) {
+  const size_t cnt = (grad || hvp) ? (hvp ? 2 * gn : gn) : 0;
+  HIP_TRY(hipMemcpyAsync(p->h_out, out_cost(p), 2 * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  if (cnt) HIP_TRY(hipMemcpyAsync(p->h_out + 2, src, cnt * sizeof(double), hipMemcpyDeviceToHost, p->stream));
   int status = 0;
   HIP_TRY(hipMemcpyAsync(p->h_tov, p->flags() + qhvp::kFlagStatus, sizeof(int), hipMemcpyDeviceToHost, p->stream));
   HIP_TRY(hipStreamSynchronize(p->stream));
@@ -1096,7 +1103,7 @@ qhvp_status host_forward(qhvp_problem* p, const double* G, const double* V, qhvp
   if (st) return st;
   st = core_post(p, qhvp::kPostCost, 0, 0, out_cost(p), out_cost(p) + 1, nullptr, nullptr);
   if (st) return st;
-  return finish_host_call(p, cost, fidelity, nullptr, nullptr);
+  return finish_host_call(p, nullptr, 0, cost, fidelity, nullptr, nullptr);
 }
 
 }  // namespace
@@ -1194,8 +1201,9 @@ qhvp_status qhvp_problem_create(qhvp_ctx* ctx, int n, int L, int L_ref, const do
     if (e != hipSuccess) { p->ws = nullptr; return cleanup_fail(QHVP_ERR_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e)); }
   }
   const size_t amp = p->amp();
-  const size_t in_bytes = std::max({(size_t)p->K * 64 * sizeof(double), (size_t)Kr * 16 * amp, (size_t)n_samples * n * 2 * amp});
-  const size_t out_bytes = (2 + (size_t)p->K * 64) * sizeof(double);
+  const size_t gl = (size_t)std::max(p->K, L);   // gates, or layers of a translationally invariant call
+  const size_t in_bytes = std::max({gl * 64 * sizeof(double), (size_t)Kr * 16 * amp, (size_t)n_samples * n * 2 * amp});
+  const size_t out_bytes = (2 + gl * 64) * sizeof(double);
   const size_t tov_bytes = std::max((size_t)n_samples * 4, (size_t)qhvp::kFlagCount) * sizeof(double);
   if (!(p->h_in = pool_pinned(ctx, in_bytes, &p->h_in_bytes)) ||
       !(p->h_out = (double*)pool_pinned(ctx, out_bytes, &p->h_out_bytes)) ||
@@ -1245,7 +1253,7 @@ qhvp_status qhvp_cost(qhvp_problem* p, const double* G, double* cost, double* fi
   if (st) return st;
   st = core_post(p, qhvp::kPostCost, 0, 0, out_cost(p), out_cost(p) + 1, nullptr, nullptr);
   if (st) return st;
-  return finish_host_call(p, cost, fidelity, nullptr, nullptr);
+  return finish_host_call(p, nullptr, 0, cost, fidelity, nullptr, nullptr);
 }
 
 qhvp_status qhvp_forward(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
@@ -1260,7 +1268,7 @@ qhvp_status qhvp_backward(qhvp_problem* p, double* grad, double* hvp) {
   if (hvp && !p->fwd_tangent) return fail(QHVP_ERR_INVALID, "the last forward sweep had no direction V");
   qhvp_status st = core_backward(p, nullptr, nullptr, grad ? out_grad(p) : nullptr, hvp ? out_hvp(p) : nullptr);
   if (st) return st;
-  return finish_host_call(p, nullptr, nullptr, grad, hvp);
+  return finish_host_call(p, out_grad(p), (size_t)p->K * 32, nullptr, nullptr, grad, hvp);
 }
 
 qhvp_status qhvp_hvp_batch(qhvp_problem* p, const double* G, int n_dirs, const double* V, qhvp_geometry geom,
@@ -1314,7 +1322,7 @@ qhvp_status qhvp_grad(qhvp_problem* p, const double* G, qhvp_geometry geom, doub
   if (st) return st;
   st = core_backward(p, out_cost(p), out_cost(p) + 1, out_grad(p), nullptr);
   if (st) return st;
-  return finish_host_call(p, cost, fidelity, grad, nullptr);
+  return finish_host_call(p, out_grad(p), (size_t)p->K * 32, cost, fidelity, grad, nullptr);
 }
 
 qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geometry geom, double* cost,
@@ -1330,7 +1338,7 @@ qhvp_status qhvp_hvp(qhvp_problem* p, const double* G, const double* V, qhvp_geo
   if (st) return st;
   st = core_backward(p, out_cost(p), out_cost(p) + 1, out_grad(p), out_hvp(p));
   if (st) return st;
-  return finish_host_call(p, cost, fidelity, grad, hvp);
+  return finish_host_call(p, out_grad(p), (size_t)p->K * 32, cost, fidelity, grad, hvp);
 }
 
 // ---- device-pointer calls: inputs and outputs in device memory, enqueued on the problem's stream
@@ -1466,70 +1474,85 @@ qhvp_status qhvp_device_status(qhvp_problem* p, int* status) {
 extern "C" {
 
 // ---- translationally invariant circuits (App. E): one gate G_(l) per layer ----------------------
+// The layer gates (and directions) are expanded to the K gates on the device, the evaluation runs as
+// for any circuit, and the per-gate derivatives (post-processed, so Riemannian ones already
+// projected at G_(l) with the projected V_(l): both maps are linear in the derivatives) are summed
+// per layer on the device in FP64 in a fixed order.
 
 namespace {
-// gate k of the brickwall belongs to layer layer_of[k]
-std::vector<int> gate_layers(int n, int L) {
-  std::vector<int> out;
-  for (int l = 0; l < L; ++l)
-    for (int q = l % 2; q + 1 < n; q += 2) out.push_back(l);
-  return out;
+qhvp_status check_ti_layers(const qhvp_problem* p, const double* G_layers, const double* V_layers, qhvp_geometry geom) {
+  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
+  if (!G_layers) return fail(QHVP_ERR_INVALID, "G_layers is NULL");
+  if (!finite_all(G_layers, (size_t)p->L * 32)) return fail(QHVP_ERR_INVALID, "G_layers has non-finite entries");
+  if (V_layers) {
+    if (!p->tangent) return fail(QHVP_ERR_UNSUPPORTED, "problem was created without tangent storage");
+    if (!finite_all(V_layers, (size_t)p->L * 32)) return fail(QHVP_ERR_INVALID, "V_layers has non-finite entries");
+  }
+  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->L, G_layers) > 1e-10)
+    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
+  return QHVP_OK;
 }
-void ti_expand(const qhvp_problem* p, const double* layers, std::vector<double>& gates) {
-  const auto lay = gate_layers(p->n, p->L);
-  gates.resize((size_t)p->K * 32);
-  for (int k = 0; k < p->K; ++k) std::memcpy(&gates[(size_t)k * 32], layers + (size_t)lay[k] * 32, 32 * sizeof(double));
+
+// The whole translationally invariant evaluation on device inputs (L*16 complex each) into device
+// outputs (grad_layers may be null; hvp_layers only with d_Vl).
+qhvp_status core_ti(qhvp_problem* p, const double* d_Gl, const double* d_Vl, int riem, double* d_cost, double* d_fid,
+                    double* d_gl, double* d_hl) {
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  LAUNCH_TRY(qhvp::launch_ti_expand(d_Gl, p->n, p->K, p->dbuf(p->lay.o_gin), p->stream));
+  if (d_Vl) LAUNCH_TRY(qhvp::launch_ti_expand(d_Vl, p->n, p->K, p->dbuf(p->lay.o_vin), p->stream));
+  qhvp_status st = core_forward(p, p->dbuf(p->lay.o_gin), d_Vl ? p->dbuf(p->lay.o_vin) : nullptr, riem, d_Vl ? 2 : 1);
+  if (st) return st;
+  st = core_backward(p, d_cost, d_fid, d_gl ? out_grad(p) : nullptr, d_hl ? out_hvp(p) : nullptr);
+  if (st) return st;
+  if (d_gl) LAUNCH_TRY(qhvp::launch_ti_reduce(out_grad(p), p->n, p->L, p->flags(), d_gl, p->stream));
+  if (d_hl) LAUNCH_TRY(qhvp::launch_ti_reduce(out_hvp(p), p->n, p->L, p->flags(), d_hl, p->stream));
+  return QHVP_OK;
 }
-void ti_reduce(const qhvp_problem* p, const double* per_gate, double* layers) {
-  const auto lay = gate_layers(p->n, p->L);
-  std::memset(layers, 0, (size_t)p->L * 32 * sizeof(double));
-  for (int k = 0; k < p->K; ++k)
-    for (int e = 0; e < 32; ++e) layers[(size_t)lay[k] * 32 + e] += per_gate[(size_t)k * 32 + e];
+
+qhvp_status host_ti(qhvp_problem* p, const double* G_layers, const double* V_layers, qhvp_geometry geom, double* cost,
+                    double* fidelity, double* grad_layers, double* hvp_layers) {
+  qhvp_status st = check_ti_layers(p, G_layers, V_layers, geom);
+  if (st) return st;
+  HIP_TRY(hipSetDevice(p->ctx->device));
+  const size_t lb = (size_t)p->L * 32 * sizeof(double);
+  double* d_in = p->dbuf(p->lay.o_tiin);
+  double* d_out = p->dbuf(p->lay.o_tiout);
+  std::memcpy(p->h_in, G_layers, lb);
+  if (V_layers) std::memcpy((char*)p->h_in + lb, V_layers, lb);
+  HIP_TRY(hipMemcpyAsync(d_in, p->h_in, V_layers ? 2 * lb : lb, hipMemcpyHostToDevice, p->stream));
+  st = core_ti(p, d_in, V_layers ? d_in + (size_t)p->L * 32 : nullptr, geom == QHVP_RIEMANNIAN, out_cost(p),
+               out_cost(p) + 1, (grad_layers || hvp_layers) ? d_out : nullptr, hvp_layers ? d_out + (size_t)p->L * 32 : nullptr);
+  if (st) return st;
+  return finish_host_call(p, d_out, (size_t)p->L * 32, cost, fidelity, grad_layers, hvp_layers);
 }
 }  // namespace
 
-qhvp_status qhvp_grad_ti(qhvp_problem* p, const double* G_layers, qhvp_geometry geom, double* cost,
+qhvp_status qhvp_grad_ti(qhvp_problem* p, const double* G_layers, qhvp_geometry geom, double* cost, double* fidelity,
                          double* grad_layers) {
-  if (!p || !G_layers || !grad_layers) return fail(QHVP_ERR_INVALID, "bad arguments");
-  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
-  if (!finite_all(G_layers, (size_t)p->L * 32)) return fail(QHVP_ERR_INVALID, "G_layers has non-finite entries");
-  if (geom == QHVP_RIEMANNIAN && qhvp_unitarity_error(p->L, G_layers) > 1e-10)
-    return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
-  std::vector<double> G, g((size_t)p->K * 32), gl((size_t)p->L * 32);
-  ti_expand(p, G_layers, G);
-  qhvp_status st = qhvp_grad(p, G.data(), QHVP_EUCLIDEAN, cost, nullptr, g.data());
-  if (st) return st;
-  ti_reduce(p, g.data(), gl.data());
-  if (geom == QHVP_RIEMANNIAN) return qhvp_project(p->L, G_layers, gl.data(), grad_layers);
-  std::memcpy(grad_layers, gl.data(), gl.size() * sizeof(double));
-  return QHVP_OK;
+  if (!p || !grad_layers) return fail(QHVP_ERR_INVALID, "bad arguments");
+  return host_ti(p, G_layers, nullptr, geom, cost, fidelity, grad_layers, nullptr);
 }
 
 qhvp_status qhvp_hvp_ti(qhvp_problem* p, const double* G_layers, const double* V_layers, qhvp_geometry geom,
-                        double* cost, double* grad_layers, double* hvp_layers) {
-  if (!p || !G_layers || !V_layers || !hvp_layers) return fail(QHVP_ERR_INVALID, "bad arguments");
-  if (geom != QHVP_EUCLIDEAN && geom != QHVP_RIEMANNIAN) return fail(QHVP_ERR_INVALID, "unknown geometry");
-  if (!finite_all(G_layers, (size_t)p->L * 32) || !finite_all(V_layers, (size_t)p->L * 32))
-    return fail(QHVP_ERR_INVALID, "non-finite layer gates or directions");
-  std::vector<double> Vl(V_layers, V_layers + (size_t)p->L * 32);
-  if (geom == QHVP_RIEMANNIAN) {
-    if (qhvp_unitarity_error(p->L, G_layers) > 1e-10) return fail(QHVP_ERR_INVALID, "Riemannian geometry needs unitary gates");
-    qhvp_project(p->L, G_layers, V_layers, Vl.data());   // tangent direction first (App. F)
-  }
-  std::vector<double> G, V, g((size_t)p->K * 32), h((size_t)p->K * 32), gl((size_t)p->L * 32), hl((size_t)p->L * 32);
-  ti_expand(p, G_layers, G);
-  ti_expand(p, Vl.data(), V);
-  qhvp_status st = qhvp_hvp(p, G.data(), V.data(), QHVP_EUCLIDEAN, cost, nullptr, g.data(), h.data());
+                        double* cost, double* fidelity, double* grad_layers, double* hvp_layers) {
+  if (!p || !V_layers || !hvp_layers) return fail(QHVP_ERR_INVALID, "bad arguments");
+  return host_ti(p, G_layers, V_layers, geom, cost, fidelity, grad_layers, hvp_layers);
+}
+
+qhvp_status qhvp_grad_ti_dev(qhvp_problem* p, const double* d_G_layers, qhvp_geometry geom, double* d_cost,
+                             double* d_fidelity, double* d_grad_layers) {
+  if (!d_grad_layers) return fail(QHVP_ERR_INVALID, "grad_layers is NULL");
+  qhvp_status st = check_dev_call(p, d_G_layers, nullptr, geom, {d_cost, d_fidelity, d_grad_layers});
   if (st) return st;
-  ti_reduce(p, g.data(), gl.data());
-  ti_reduce(p, h.data(), hl.data());
-  if (geom == QHVP_RIEMANNIAN) {
-    if (grad_layers) qhvp_project(p->L, G_layers, gl.data(), grad_layers);
-    return qhvp_riemannian_hvp(p->L, G_layers, gl.data(), hl.data(), Vl.data(), hvp_layers);
-  }
-  if (grad_layers) std::memcpy(grad_layers, gl.data(), gl.size() * sizeof(double));
-  std::memcpy(hvp_layers, hl.data(), hl.size() * sizeof(double));
-  return QHVP_OK;
+  return core_ti(p, d_G_layers, nullptr, geom == QHVP_RIEMANNIAN, d_cost, d_fidelity, d_grad_layers, nullptr);
+}
+
+qhvp_status qhvp_hvp_ti_dev(qhvp_problem* p, const double* d_G_layers, const double* d_V_layers, qhvp_geometry geom,
+                            double* d_cost, double* d_fidelity, double* d_grad_layers, double* d_hvp_layers) {
+  if (!d_hvp_layers || !d_V_layers) return fail(QHVP_ERR_INVALID, "V_layers and hvp_layers must not be NULL");
+  qhvp_status st = check_dev_call(p, d_G_layers, d_V_layers, geom, {d_cost, d_fidelity, d_grad_layers, d_hvp_layers});
+  if (st) return st;
+  return core_ti(p, d_G_layers, d_V_layers, geom == QHVP_RIEMANNIAN, d_cost, d_fidelity, d_grad_layers, d_hvp_layers);
 }
 
 qhvp_status qhvp_overlaps(const qhvp_problem* p, double* T, double* Omega) {

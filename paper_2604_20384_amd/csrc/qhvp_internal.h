@@ -174,6 +174,18 @@ int launch_prep(const PrepArgs& a, void* stream);
 int launch_post(const PostArgs& a, void* stream);
 // dst = src (n_complex complex FP64 values, device) in the given precision.
 int launch_convert(const double* src, void* dst, long long n_complex, int prec, void* stream);
+// Translationally invariant brickwalls (App. E).  The K gates of a brickwall are numbered layer by
+// layer, and within a layer by their first qubit: even layers hold the n/2 gates on (0,1), (2,3), ...,
+// odd layers the (n-1)/2 gates on (1,2), (3,4), ...; so a pair of layers holds n-1 gates.
+constexpr int ti_first_gate(int l, int n) { return (l / 2) * (n - 1) + ((l & 1) ? n / 2 : 0); }
+constexpr int ti_gate_count(int l, int n) { return (l & 1) ? (n - 1) / 2 : n / 2; }
+constexpr int ti_layer_of(int k, int n) { return 2 * (k / (n - 1)) + ((k % (n - 1)) >= n / 2 ? 1 : 0); }
+// gates[k] = layers[ti_layer_of(k, n)] for the K gates of
+// an n-qubit brickwall (16 complex FP64 per gate, device).
+int launch_ti_expand(const double* layers, int n, int K, double* gates, void* stream);
+// out[l] = sum over the gates k of layer l, in increasing k, of per_gate[k] (16 complex FP64 each;
+// L layers); a layer without gates gives zero.  Nothing is written if flags[kFlagStatus] != 0.
+int launch_ti_reduce(const double* per_gate, int n, int L, const int* flags, double* out, void* stream);
 
 // Scratch of the entry point that allocates nothing (a file-scope device array in qhvp_post.hip).
 constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;

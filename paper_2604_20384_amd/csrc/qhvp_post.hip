@@ -294,6 +294,25 @@ __global__ void k_convert(const double* __restrict__ src, void* dst, long long n
   }
 }
 
+// Translationally invariant brickwalls (App. E): expansion of the layer gates and the per-layer sums.
+__global__ void k_ti_expand(const double* __restrict__ layers, int n, int K, double* __restrict__ gates) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < K * 32; i += gridDim.x * blockDim.x)
+    gates[i] = layers[32 * ti_layer_of(i >> 5, n) + (i & 31)];
+}
+
+// The derivative with respect to a layer gate is the sum of the derivatives with respect to the
+// gates it stands for; one thread per real entry, the layer's gates added in increasing order.
+__global__ void k_ti_reduce(const double* __restrict__ per_gate, int n, int L, const int* __restrict__ flags,
+                            double* __restrict__ out) {
+  if (flags[kFlagStatus] != 0) return;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < L * 32; i += gridDim.x * blockDim.x) {
+    const int l = i >> 5, e = i & 31, k0 = ti_first_gate(l, n), cnt = ti_gate_count(l, n);
+    double s = 0;
+    for (int c = 0; c < cnt; ++c) s += per_gate[32 * (k0 + c) + e];
+    out[i] = s;
+  }
+}
+
 // The scratch of the entry point that allocates nothing: every problem evaluated through it lives
 // here (labels, states, partial sums, flags).  Each device that loads the library holds its own copy
 // of this array until the process ends; host code uses only the address looked up per device below,
@@ -325,6 +344,19 @@ int launch_convert(const double* src, void* dst, long long n_complex, int prec, 
   if (n_complex <= 0) return (int)hipSuccess;
   const long long blocks = std::min<long long>((n_complex + 255) / 256, 1024);
   hipLaunchKernelGGL(k_convert, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream, src, dst, n_complex, prec);
+  return (int)hipGetLastError();
+}
+
+int launch_ti_expand(const double* layers, int n, int K, double* gates, void* stream) {
+  if (K <= 0) return (int)hipSuccess;
+  hipLaunchKernelGGL(k_ti_expand, dim3((unsigned)((K * 32 + 255) / 256)), dim3(256), 0, (hipStream_t)stream, layers, n, K,
+                     gates);
+  return (int)hipGetLastError();
+}
+int launch_ti_reduce(const double* per_gate, int n, int L, const int* flags, double* out, void* stream) {
+  if (L <= 0) return (int)hipSuccess;
+  hipLaunchKernelGGL(k_ti_reduce, dim3((unsigned)((L * 32 + 255) / 256)), dim3(256), 0, (hipStream_t)stream, per_gate, n, L,
+                     flags, out);
   return (int)hipGetLastError();
 }
 

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/qhvp.h"
+#include "../../paper_2604_20384_amd/csrc/qhvp_internal.h"
 
 extern "C" void stub_fail_allocations(int device_calls, int pinned_calls);
 extern "C" void stub_fail_pinned_nth(int nth);
@@ -39,6 +40,23 @@ static std::vector<double> random_gates(int K, bool unitary) {
     if (qhvp_retract(K, g.data(), z.data(), u.data()) == QHVP_OK) return u;
   }
   return g;
+}
+
+// The layer arithmetic the translationally invariant kernels use, against the brickwall's gates
+// enumerated layer by layer (App. E's layer sets).
+static void ti_layers() {
+  for (int n = 2; n <= 30; ++n)
+    for (int L : {1, 2, 3, 4, 7, 20, 41}) {
+      int k = 0;
+      for (int l = 0; l < L; ++l) {
+        CHECK(qhvp::ti_first_gate(l, n) == k);
+        int cnt = 0;
+        for (int q = l % 2; q + 1 < n; q += 2, ++k, ++cnt) CHECK(qhvp::ti_layer_of(k, n) == l);
+        CHECK(qhvp::ti_gate_count(l, n) == cnt);
+      }
+      CHECK(k == qhvp_num_gates(n, L));
+    }
+  std::puts("OK ti layers");
 }
 
 static void plans() {
@@ -157,10 +175,17 @@ static void call_sequences() {
       std::vector<double> hs(Vs.size());
       CHECK(qhvp_hvp_batch(p, G.data(), 3, Vs.data(), QHVP_EUCLIDEAN, &c, g.data(), hs.data()) == QHVP_OK);
       CHECK(qhvp_overlaps(p, T.data(), Om.data()) == QHVP_OK);
-      std::vector<double> Gl((size_t)L * 32), gl((size_t)L * 32), hl((size_t)L * 32);
+      std::vector<double> gl((size_t)L * 32), hl((size_t)L * 32);
+      double keep_ti = 0;
       auto Gl0 = random_gates(L, true);
-      CHECK(qhvp_grad_ti(p, Gl0.data(), QHVP_EUCLIDEAN, &c, gl.data()) == QHVP_OK);
-      CHECK(qhvp_hvp_ti(p, Gl0.data(), Gl0.data(), QHVP_RIEMANNIAN, &c, gl.data(), hl.data()) == QHVP_OK);
+      CHECK(qhvp_grad_ti(p, Gl0.data(), QHVP_EUCLIDEAN, &c, &F, gl.data()) == QHVP_OK);
+      CHECK(qhvp_hvp_ti(p, Gl0.data(), Gl0.data(), QHVP_RIEMANNIAN, &c, nullptr, gl.data(), hl.data()) == QHVP_OK);
+      CHECK(qhvp_hvp_ti(p, Gl0.data(), Gl0.data(), QHVP_EUCLIDEAN, nullptr, nullptr, nullptr, hl.data()) == QHVP_OK);
+      auto Gl1 = Gl0;
+      Gl1[5] = NAN;
+      keep_ti = 2.5;
+      CHECK(qhvp_grad_ti(p, Gl1.data(), QHVP_EUCLIDEAN, &keep_ti, nullptr, gl.data()) == QHVP_ERR_INVALID && keep_ti == 2.5);
+      CHECK(qhvp_hvp_ti(p, Gl0.data(), nullptr, QHVP_EUCLIDEAN, nullptr, nullptr, nullptr, hl.data()) == QHVP_ERR_INVALID);
       double ms = 0, by = 0, fl = 0;
       long long cnt = 0;
       for (int kind = 0; kind < QHVP_KERNEL_KINDS; ++kind) CHECK(qhvp_kernel_stats(p, kind, &ms, &cnt, &by, &fl) == QHVP_OK);
@@ -191,6 +216,14 @@ static void call_sequences() {
       CHECK(qhvp_backward_dev(p, dout + 2, dout + 2 + G.size()) == QHVP_OK);
       CHECK(qhvp_hvp_dev(p, G.data(), dV, QHVP_EUCLIDEAN, nullptr, nullptr, nullptr, dout + 2) == QHVP_ERR_INVALID);
       CHECK(qhvp_hvp_dev(p, dG, dV, QHVP_EUCLIDEAN, nullptr, nullptr, nullptr, h.data()) == QHVP_ERR_INVALID);
+      double *dGl = nullptr, *dlo = nullptr;
+      CHECK(hipMalloc((void**)&dGl, Gl0.size() * 8) == 0 && hipMalloc((void**)&dlo, (2 + 2 * Gl0.size()) * 8) == 0);
+      std::memcpy(dGl, Gl0.data(), Gl0.size() * 8);
+      CHECK(qhvp_grad_ti_dev(p, dGl, QHVP_RIEMANNIAN, dlo, dlo + 1, dlo + 2) == QHVP_OK);
+      CHECK(qhvp_hvp_ti_dev(p, dGl, dGl, QHVP_EUCLIDEAN, nullptr, nullptr, nullptr, dlo + 2 + Gl0.size()) == QHVP_OK);
+      CHECK(qhvp_hvp_ti_dev(p, Gl0.data(), dGl, QHVP_EUCLIDEAN, nullptr, nullptr, nullptr, dlo + 2) == QHVP_ERR_INVALID);
+      CHECK(qhvp_grad_ti_dev(p, dGl, QHVP_EUCLIDEAN, nullptr, nullptr, gl.data()) == QHVP_ERR_INVALID);
+      hipFree(dGl); hipFree(dlo);
       int status = -1;
       CHECK(qhvp_device_status(p, &status) == QHVP_OK);
       // the allocation-free entry point: a small problem runs, a large one is refused
@@ -211,6 +244,7 @@ static void call_sequences() {
 }
 
 int main() {
+  ti_layers();
   plans();
   utilities();
   creation_errors();

@@ -113,6 +113,8 @@ int launch_reduce_env(const double*, int, int, const int*, const PassDesc&, doub
 int launch_prep(const PrepArgs&, void*) { return 0; }
 int launch_post(const PostArgs&, void*) { return 0; }
 int launch_convert(const double*, void*, long long, int, void*) { return 0; }
+int launch_ti_expand(const double*, int, int, double*, void*) { return 0; }
+int launch_ti_reduce(const double*, int, int, const int*, double*, void*) { return 0; }
 int noalloc_scratch_init(int) { return 0; }
 void* noalloc_scratch(int) {
   std::lock_guard<std::mutex> l(g_mu);
