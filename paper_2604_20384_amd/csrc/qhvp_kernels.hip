@@ -199,6 +199,11 @@ template <> struct Lds<double2> {
 typedef float qv4f __attribute__((ext_vector_type(4)));
 typedef double qv2d __attribute__((ext_vector_type(2)));
 
+// Global state traffic: every state array a pass touches is read or written once per pass and is
+// many times larger than the caches, so these accesses are marked non-temporal (streaming).
+template <typename V> __device__ __forceinline__ V gld(const V* p) { return __builtin_nontemporal_load(p); }
+template <typename V> __device__ __forceinline__ void gst(V* p, V v) { __builtin_nontemporal_store(v, p); }
+
 template <typename T> struct TileIO {
   using V = typename std::conditional<sizeof(T) == 8, qv4f, qv2d>::type;   // 16 bytes
   static constexpr int EPV = 16 / (int)sizeof(T);
@@ -242,7 +247,7 @@ template <typename T> struct TileIO {
   static __device__ __forceinline__ void load(T* lds, const T* g, long long base, const int* xv, int TS, int tid) {
     V r[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) r[v] = *(const V*)(g + base + xv[v]);
+    for (int v = 0; v < NV; ++v) r[v] = gld((const V*)(g + base + xv[v]));
 #pragma unroll
     for (int v = 0; v < NV; ++v) put(lds, elem(tid, v), TS, r[v]);
   }
@@ -250,7 +255,7 @@ template <typename T> struct TileIO {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       const V r = get(lds, elem(tid, v));
-      if (elem(tid, v) < TS) *(V*)(g + base + xv[v]) = r;
+      if (elem(tid, v) < TS) gst((V*)(g + base + xv[v]), r);
     }
   }
   // Stores split in two halves (LDS -> registers, registers -> memory), so that a tile's global
@@ -262,7 +267,7 @@ template <typename T> struct TileIO {
   static __device__ __forceinline__ void write(T* g, const V (&r)[NV], long long base, const int* xv, int TS, int tid) {
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      if (elem(tid, v) < TS) *(V*)(g + base + xv[v]) = r[v];
+      if (elem(tid, v) < TS) gst((V*)(g + base + xv[v]), r[v]);
   }
 };
 
@@ -658,8 +663,8 @@ __global__ void __launch_bounds__(kThreads)
   {                                                                                                 \
     const long long bn_ = (long long)(S) * dim + (X);                                               \
     _Pragma("unroll") for (int v = 0; v < IO::NV; ++v) {                                            \
-      pf0[v] = *(const typename IO::V*)(srcP + bn_ + xv[v]);                                        \
-      if (TANG) pf1[v] = *(const typename IO::V*)(srcD + bn_ + xv[v]);                              \
+      pf0[v] = gld((const typename IO::V*)(srcP + bn_ + xv[v]));                                    \
+      if (TANG) pf1[v] = gld((const typename IO::V*)(srcD + bn_ + xv[v]));                          \
     }                                                                                               \
   }
   if (!gen && c < nch) QHVP_FWD_PREFETCH(s, x);
@@ -763,7 +768,7 @@ __global__ void __launch_bounds__(kThreads)
       double tr = 0, ti = 0, orr = 0, oi = 0;
       typename IO::V ph[IO::NV];
 #pragma unroll
-      for (int v = 0; v < IO::NV; ++v) ph[v] = *(const typename IO::V*)(phi0 + base + xv[v]);
+      for (int v = 0; v < IO::NV; ++v) ph[v] = gld((const typename IO::V*)(phi0 + base + xv[v]));
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v)
 #pragma unroll
@@ -1042,10 +1047,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
   {                                                                                                 \
     const long long bn_ = (long long)(S) * dim + (X);                                               \
     _Pragma("unroll") for (int v = 0; v < IO::NV; ++v) {                                            \
-      pfa[v] = *(const typename IO::V*)(abA + bn_ + xv[v]);                                         \
-      if (TANG) pfb[v] = *(const typename IO::V*)(abB + bn_ + xv[v]);                               \
-      pfp[v] = *(const typename IO::V*)(srcP + bn_ + xv[v]);                                        \
-      if (TANG) pfd[v] = *(const typename IO::V*)(srcD + bn_ + xv[v]);                              \
+      pfa[v] = gld((const typename IO::V*)(abA + bn_ + xv[v]));                                     \
+      if (TANG) pfb[v] = gld((const typename IO::V*)(abB + bn_ + xv[v]));                           \
+      pfp[v] = gld((const typename IO::V*)(srcP + bn_ + xv[v]));                                    \
+      if (TANG) pfd[v] = gld((const typename IO::V*)(srcD + bn_ + xv[v]));                          \
     }                                                                                               \
   }
   if (common && it0 < it1) QHVP_BWD_PREFETCH(s, x);
@@ -1079,7 +1084,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
       Os.x = (R)a.tov[4 * s + 2]; Os.y = (R)a.tov[4 * s + 3];
       typename IO::V ph[IO::NV];
 #pragma unroll
-      for (int v = 0; v < IO::NV; ++v) ph[v] = *(const typename IO::V*)(phi0 + base + xv[v]);
+      for (int v = 0; v < IO::NV; ++v) ph[v] = gld((const typename IO::V*)(phi0 + base + xv[v]));
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v)
 #pragma unroll
@@ -1384,7 +1389,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       Os.x = (R)a.tov[4 * s + 2]; Os.y = (R)a.tov[4 * s + 3];
       typename IO::V ph[IO::NV];
 #pragma unroll
-      for (int v = 0; v < IO::NV; ++v) ph[v] = *(const typename IO::V*)(phi0 + base + xv[v]);
+      for (int v = 0; v < IO::NV; ++v) ph[v] = gld((const typename IO::V*)(phi0 + base + xv[v]));
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v)
 #pragma unroll
