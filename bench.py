@@ -17,7 +17,9 @@ input) and reported separately as setup time.  Further legs, reported beside the
   complex64) at rates swept over 0.25-1.2x the measured serial capacity, served one at a time and
   with continuous batching, with throughput, p50 / p99 latency and GPU-busy fraction;
 * cpu_baseline: the oracle on the host, one single-threaded process per sample for samples 0-3 run
-  together (the same runs give the accuracy reference).
+  together (the same runs give the accuracy reference);
+* c2: the n=16, L=12, N_s=64 problem on the GPU in both precisions, and whole on P single-threaded
+  oracle processes, timed directly, with the GPU results' errors against that oracle run.
 
 Prints one JSON line.
 """
@@ -39,6 +41,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 COMPUTE_PEAK = {"c64": ("mfma", 157.3), "c128": ("alu", 78.6)}
 TRAFFIC_PROFILE = "profiles/traffic_k_bwd_out_c64.json"
 ORACLE_SAMPLES = 4
+MAX_HOST_WORKERS = 16          # host processes of the n=16 oracle run (the host share of one GPU)
 
 
 def parse():
@@ -98,6 +101,99 @@ def oracle_pool():
 def start_oracle(pool, n, L, ns, seed):
     """Samples 0..ORACLE_SAMPLES-1, one per worker."""
     return pool, pool.map_async(_oracle_sample, [(n, L, ns, seed, s) for s in range(ORACLE_SAMPLES)])
+
+
+# The configuration the oracle runs whole: n=16, L=12 (K=90), L_ref=24, N_s=64.
+C2 = (16, 12, 64)
+
+
+def _c2_worker(rank, P, seed, go, barrier, q):
+    """Samples rank, rank+P, ... of the n=16 problem through the oracle, single-threaded: labels
+    first, then (once all P workers are ready) the timed evaluation."""
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import circuit, sv
+    from paper_2604_20384_amd.inputs import make_problem
+    n, L, ns = C2
+    if not go.wait(3600):
+        return
+    with threadpool_limits(1):
+        p = make_problem(n, L, ns, seed=seed)
+        mine = list(range(rank, ns, P))
+        psi, phi = circuit.labels(p.uref, p.samples[mine], n, p.L_ref)
+        barrier.wait(600)
+        t0 = time.time()
+        out = sv.evaluate(psi, phi, p.G, p.V, n, L, batch=1)
+        t1 = time.time()
+    # sample-weighted, so that the parent adds the parts of all workers
+    w = len(mine)
+    q.put((rank, t0, t1, w * float(out["fidelity"]), w * np.asarray(out["grad"]), w * np.asarray(out["hvp"])))
+
+
+def c2_oracle_start(seed):
+    """P = the host cores this process may use (at most MAX_HOST_WORKERS); P worker processes,
+    started before this process touches the GPU, wait until c2_oracle_run releases them."""
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    P = min(MAX_HOST_WORKERS, len(os.sched_getaffinity(0)))
+    go, barrier, q = ctx.Event(), ctx.Barrier(P), ctx.Queue()
+    procs = [ctx.Process(target=_c2_worker, args=(r, P, seed, go, barrier, q), daemon=True) for r in range(P)]
+    for pr in procs:
+        pr.start()
+    # the handle keeps every shared object alive: a child unpickles them after start() returns
+    return P, go, barrier, q, procs
+
+
+def c2_oracle_run(handle):
+    """The full n=16 problem on P single-threaded processes, timed directly: from the first worker's
+    start of the evaluation to the last one's end (labels excluded, as on the GPU)."""
+    import numpy as np
+    P, go, _barrier, q, procs = handle
+    go.set()
+    parts = [q.get(timeout=900) for _ in range(P)]
+    for pr in procs:
+        pr.join(60)
+    wall = max(r[2] for r in parts) - min(r[1] for r in parts)
+    ns = C2[2]
+    ref = (sum(r[3] for r in parts) / ns, sum(r[4] for r in parts) / ns, sum(r[5] for r in parts) / ns)
+    return P, wall, (float(ref[0]), np.asarray(ref[1]), np.asarray(ref[2]))
+
+
+def c2_gpu_leg(seed, timed=10, warmup=3):
+    """The n=16 problem on the GPU in both precisions: from-scratch HVPs (a fresh Haar G per call),
+    median of `timed` individually timed calls after `warmup`; plus one call at the problem's own
+    (G, V) for the accuracy against the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2604_20384_amd.api import Problem, num_gates
+    from paper_2604_20384_amd.inputs import haar_unitary, make_problem, random_tangent
+    n, L, ns = C2
+    prob = make_problem(n, L, ns, seed=seed)
+    rng = np.random.default_rng(seed + 5000)
+    K = num_gates(n, L)
+    Gs = [haar_unitary(rng, 4, K) for _ in range(warmup + timed)]
+    Vs = [random_tangent(rng, G) for G in Gs]
+    out, results = {}, {}
+    for precision in ("c64", "c128"):
+        gp = Problem(n, L, prob.uref, prob.samples, L_ref=prob.L_ref, precision=precision, ckpt_every=0, device=0)
+        times = []
+        for i in range(warmup + timed):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gp.hvp(Gs[i], Vs[i])
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        med = float(np.median(times[warmup:]))
+        _, g, h = gp.hvp(prob.G, prob.V)
+        results[precision] = (gp.last_fidelity, g, h)
+        gp.close()
+        out[precision] = {"value": round(1.0 / med, 2), "unit": "HVP/s", "median_ms": round(1e3 * med, 3),
+                          "timed_calls": timed, "ckpt_every_layers": 0}
+    return out, results
 
 
 def cpu_info():
@@ -369,6 +465,7 @@ def main():
         copy_probe()
         return
     pool = None if args.no_cpu_baseline else oracle_pool()
+    c2_cpu = None if args.no_cpu_baseline else c2_oracle_start(args.seed)
 
     import numpy as np
     import torch
@@ -447,6 +544,9 @@ def main():
         out["c128"] = leg(prob, "c128", ck128, 4, args.seed + 3000)
         acc_gpu["c128_full"] = one_hvp(prob, "c128", ck128)
         out["accuracy"] = {"c64_vs_c128_all_samples": errors(acc_gpu["c64_full"], acc_gpu["c128_full"])}
+        c2_gpu, c2_res = c2_gpu_leg(args.seed)
+        out["c2"] = {"workload": f"brickwall HS-test HVP n={C2[0]} L={C2[1]} N_s={C2[2]} L_ref={2 * C2[1]}",
+                     "gpu": c2_gpu}
     if not args.no_serving:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         out["serving"] = serving_sweep(args.serve_requests, rates, args.seed)
@@ -460,7 +560,7 @@ def main():
         pool.join()
         t_sample = max(r[0] for r in runs)
         model, blas = cpu_info()
-        P = len(os.sched_getaffinity(0))
+        P = min(MAX_HOST_WORKERS, len(os.sched_getaffinity(0)))
         out["cpu_baseline"] = {
             "value": ORACLE_SAMPLES / (ns * t_sample), "unit": "HVP/s", "cores": ORACLE_SAMPLES, "kind": "oracle",
             "sample": f"samples 0-{ORACLE_SAMPLES - 1} of the {ns} (n={n}, L={L}, K={K}) through the numpy complex128 "
@@ -473,6 +573,17 @@ def main():
                    np.mean([r[3] for r in runs], axis=0))
             out["accuracy"]["oracle_first_4_samples"] = {"c64": errors(acc_gpu["c64_4"], ref),
                                                          "c128": errors(acc_gpu["c128_4"], ref)}
+    if c2_cpu is not None:
+        # after every GPU leg and the concurrent oracle samples, so that nothing else competes for the cores
+        P, wall, ref = c2_oracle_run(c2_cpu)
+        c2 = out.setdefault("c2", {"workload": f"brickwall HS-test HVP n={C2[0]} L={C2[1]} N_s={C2[2]} L_ref={2 * C2[1]}"})
+        c2["cpu_oracle"] = {"value": round(1.0 / wall, 4), "unit": "HVP/s", "cores": P, "kind": "oracle",
+                            "measured": f"directly: all {C2[2]} samples over {P} single-threaded processes "
+                                        f"(samples r, r+{P}, ... on process r), {wall:.2f} s from the first "
+                                        f"process's start of the evaluation to the last one's end, labels excluded"}
+        if "gpu" in c2:
+            c2["accuracy_vs_oracle_all_samples"] = {prec: errors(c2_res[prec], ref) for prec in ("c64", "c128")}
+            c2["gpu_vs_cpu"] = {prec: round(c2["gpu"][prec]["value"] * wall, 1) for prec in ("c64", "c128")}
     print(json.dumps(out), flush=True)
 
 
