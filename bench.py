@@ -9,6 +9,8 @@ input) and reported separately as setup time.  Further legs, reported beside the
 
 * fixed_G: HVPs along several directions at one G (the forward states at G are kept between calls);
 * ckpt4: the headline workload with layer checkpointing every 4 layers (rate and peak HBM);
+* rebuild: the headline workload keeping only the final forward states, the backward sweep
+  rebuilding every pass boundary by undoing the pass's gates (rate and peak HBM);
 * c128: the same workload in complex128, with its own roofline against the FP64 peak;
 * ti: the translationally invariant ansatz (one gate per layer, per-layer outputs, App. E);
 * accuracy: fidelity, gradient and HVP errors against the oracle on samples 0-3 (both precisions)
@@ -53,8 +55,9 @@ def parse():
     ap.add_argument("--L", type=int, default=20)
     ap.add_argument("--ns", type=int, default=256)
     ap.add_argument("--precision", default="c64", choices=["c64", "c128"])
-    ap.add_argument("--ckpt", type=int, default=None,
-                    help="layer checkpoint interval (0: every pass boundary; default: the fastest that fits)")
+    ap.add_argument("--ckpt", type=lambda v: v if v == "rebuild" else int(v), default=None,
+                    help="layer checkpoint interval (0: every pass boundary; 'rebuild': only the final "
+                         "states, the backward sweep rebuilds the boundaries; default: the fastest that fits)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a 2 GiB device copy 5 times (calibrates HBM traffic counters)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle runs (and the accuracy leg)")
@@ -495,7 +498,9 @@ def main():
     hvps = args.steps / dt
     ms_per_step = 1e3 * dt / args.steps
     alg_bytes_step = sum(v["bytes"] for v in stats.values()) / args.steps
-    roof = roofline(stats, args.precision, args.steps, gp, with_traffic=(n, L, ns) == (20, 20, 256))
+    # the committed traffic profile is the one of this workload with every pass boundary kept
+    roof = roofline(stats, args.precision, args.steps, gp,
+                    with_traffic=(n, L, ns) == (20, 20, 256) and args.ckpt == 0 and args.precision == "c64")
 
     out = {
         "metric": "HVPs/sec (n=20, L=20, N_s=256)",
@@ -540,10 +545,13 @@ def main():
         acc_gpu["c128_4"] = one_hvp(prob, "c128", 0, ns=ORACLE_SAMPLES)
         out["ckpt4"] = leg(prob, "c64", 4, 5, args.seed + 2000)
         out["ti"] = ti_leg(prob, 5, args.seed + 4000, hvps)
+        out["rebuild"] = leg(prob, "c64", "rebuild", 5, args.seed + 6000)
         ck128 = pick_ckpt(n, L, prob.L_ref, ns, "c128")
         out["c128"] = leg(prob, "c128", ck128, 4, args.seed + 3000)
         acc_gpu["c128_full"] = one_hvp(prob, "c128", ck128)
-        out["accuracy"] = {"c64_vs_c128_all_samples": errors(acc_gpu["c64_full"], acc_gpu["c128_full"])}
+        out["accuracy"] = {"c64_vs_c128_all_samples": errors(acc_gpu["c64_full"], acc_gpu["c128_full"]),
+                           "c64_rebuild_vs_c128_all_samples": errors(one_hvp(prob, "c64", "rebuild"),
+                                                                     acc_gpu["c128_full"])}
         c2_gpu, c2_res = c2_gpu_leg(args.seed)
         out["c2"] = {"workload": f"brickwall HS-test HVP n={C2[0]} L={C2[1]} N_s={C2[2]} L_ref={2 * C2[1]}",
                      "gpu": c2_gpu}

@@ -108,9 +108,17 @@ void qhvp_ctx_destroy(qhvp_ctx* ctx);
  *                    (layer checkpointing; Alg. 1 keeps every state instead).
  *   ckpt_every = 0 : keep the state at every pass boundary (no recomputation).
  *   ckpt_every < 0 : segments of -ckpt_every passes.
+ *   ckpt_every = QHVP_CKPT_REBUILD : keep only the final forward states; the backward sweep
+ *                    rebuilds every pass boundary from the one after it by undoing the pass's
+ *                    gates (Eq. fis / Eq. dfis solved for the input states), so no boundary is
+ *                    stored and none is recomputed: the speed of ckpt_every = 0 in the memory of
+ *                    five state sets.  It needs gates that are unitary up to a scale to about
+ *                    1e-6 (|G|_F |G^-1|_F <= 4 (1 + 1e-6)); gradient and HVP calls with other gates
+ *                    fail on the device (QHVP_DEV_NOT_INVERTIBLE) and leave their outputs untouched.
  *   with_tangent   : 1 to allow qhvp_hvp (stores the tangent states too).
  * Returns 0 on invalid arguments.
  */
+#define QHVP_CKPT_REBUILD (-(1 << 30))
 size_t qhvp_workspace_bytes(int n, int L, int L_ref, int n_samples, qhvp_precision prec,
                             int ckpt_every, int with_tangent);
 
@@ -197,9 +205,10 @@ qhvp_status qhvp_hvp_noalloc(qhvp_ctx* ctx, int n, int L, int L_ref, const doubl
                              void* hip_stream);
 
 /* Device-side input check of the last call (waits for the problem's stream): 0 if its inputs were
- * valid, else an OR of QHVP_DEV_NONFINITE and QHVP_DEV_NOT_UNITARY. */
+ * valid, else an OR of the QHVP_DEV_* reasons. */
 #define QHVP_DEV_NONFINITE 1    /* a non-finite entry in G or V */
 #define QHVP_DEV_NOT_UNITARY 2  /* Riemannian geometry with |G_k^dag G_k - I|_F > 1e-10 for some k */
+#define QHVP_DEV_NOT_INVERTIBLE 4 /* QHVP_CKPT_REBUILD with a gate beyond its bound on |G|_F |G^-1|_F */
 qhvp_status qhvp_device_status(qhvp_problem* p, int* status);
 
 /* Fixed-G reuse and several directions (Sec. IV: the truncated-CG inner loop takes many HVPs at

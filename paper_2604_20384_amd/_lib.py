@@ -20,6 +20,8 @@ LIB_PATH = os.environ.get("QHVP_LIB", os.path.join(_HERE, "libqhvp.so"))
 
 QHVP_OK, QHVP_ERR_INVALID, QHVP_ERR_NOMEM, QHVP_ERR_DEVICE, QHVP_ERR_UNSUPPORTED = range(5)
 QHVP_C128, QHVP_C64_ACC64 = 0, 1
+QHVP_CKPT_REBUILD = -(1 << 30)
+QHVP_DEV_NONFINITE, QHVP_DEV_NOT_UNITARY, QHVP_DEV_NOT_INVERTIBLE = 1, 2, 4
 QHVP_EUCLIDEAN, QHVP_RIEMANNIAN = 0, 1
 
 _STATUS_NAMES = {0: "OK", 1: "INVALID", 2: "NOMEM", 3: "DEVICE", 4: "UNSUPPORTED"}

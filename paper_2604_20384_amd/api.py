@@ -17,6 +17,7 @@ from . import _lib
 from ._lib import check, dptr, lib
 
 PRECISIONS = {"c128": _lib.QHVP_C128, "c64": _lib.QHVP_C64_ACC64}
+CKPT_REBUILD = _lib.QHVP_CKPT_REBUILD
 
 
 def num_gates(n: int, L: int) -> int:
@@ -37,8 +38,13 @@ def plan(n: int, L: int):
     return list(per), list(order)
 
 
+def _ckpt(ckpt_every) -> int:
+    """The library's checkpoint setting: an int, or "rebuild" (QHVP_CKPT_REBUILD)."""
+    return CKPT_REBUILD if ckpt_every == "rebuild" else int(ckpt_every)
+
+
 def workspace_bytes(n, L, L_ref, n_samples, precision="c128", ckpt_every=1, with_tangent=True) -> int:
-    return int(lib.qhvp_workspace_bytes(n, L, L_ref, n_samples, PRECISIONS[precision], ckpt_every,
+    return int(lib.qhvp_workspace_bytes(n, L, L_ref, n_samples, PRECISIONS[precision], _ckpt(ckpt_every),
                                         1 if with_tangent else 0))
 
 
@@ -90,7 +96,9 @@ class Problem:
     uref        : (K_ref, 4, 4) gates of the reference brickwall of L_ref layers.
     samples     : (N_s, n, 2) single-qubit states of the product-state samples.
     precision   : "c128" or "c64" (complex64 states, FP64 accumulation).
-    ckpt_every  : layer-checkpoint interval (0 = keep every pass boundary).
+    ckpt_every  : layer-checkpoint interval (0 = keep every pass boundary, c > 0 every c layers,
+                  -c every c passes), or "rebuild": keep only the final forward states and let the
+                  backward sweep rebuild the pass boundaries (gates unitary up to a scale).
     workspace   : "torch" (allocate with torch), a (device pointer, bytes) block owned by the
                   caller, or None (the library allocates).
     """
@@ -129,7 +137,7 @@ class Problem:
         self.stream = stream if stream is not None else torch.cuda.current_stream(device)
         h = C.c_void_p()
         check(lib.qhvp_problem_create(self.ctx.handle, n, L, L_ref, dptr(_f64(uref)), dptr(_f64(samples)),
-                                      self.n_samples, PRECISIONS[precision], ckpt_every,
+                                      self.n_samples, PRECISIONS[precision], _ckpt(ckpt_every),
                                       1 if with_tangent else 0, ws_ptr, self.ws_bytes,
                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.handle = h

@@ -370,6 +370,7 @@ std::vector<std::pair<int, int>> plan_segments(int n, int L, int ckpt_every) {
 
 struct Layout {
   size_t state_bytes = 0;   // one state set: N_s * 2^n amplitudes
+  int rebuild = 0;          // QHVP_CKPT_REBUILD: one slot for the forward states, rebuilt backwards
   int n_ckpt = 0;           // stored segment-start checkpoints (segments 1..J-1)
   int n_seg = 0;            // in-segment boundary buffers (max segment length - 1)
   int slot_states = 1;      // state sets per slot (2 with tangent)
@@ -401,8 +402,9 @@ bool make_layout(int n, int L, int L_ref, int Ns, qhvp_precision prec, int ckpt_
   lay.state_bytes = align_up((size_t)Ns * ((size_t)1 << n) * amp);
   lay.slot_states = tangent ? 2 : 1;
   lay.slot_bytes = lay.state_bytes * lay.slot_states;
-  lay.n_ckpt = (int)seg.size() - 1;
-  lay.n_seg = maxlen - 1;
+  lay.rebuild = ckpt_every == QHVP_CKPT_REBUILD ? 1 : 0;
+  lay.n_ckpt = lay.rebuild ? 0 : (int)seg.size() - 1;
+  lay.n_seg = lay.rebuild ? 1 : maxlen - 1;   // rebuilding: the one forward-state slot
   const int mb = std::min(n, qhvp::kMaxTileBits);
   lay.tiles_max = 1 << (n - mb);
   lay.n_wg_max = qhvp::grid_size((long long)Ns * lay.tiles_max);
@@ -591,6 +593,9 @@ struct qhvp_problem {
   // boundaries 1..maxlen-1; last: working / backward (a, b)
   char* ckpt(int segment) { return slot(segment - 1); }
   char* segbuf(int i) { return slot(lay.n_ckpt + i - 1); }
+  // QHVP_CKPT_REBUILD: the forward states, overwritten pass by pass (forward sweep: each pass's
+  // output; backward sweep: each pass's input, rebuilt)
+  char* rebuilt() { return segbuf(1); }
   char* work() { return slot(lay.n_ckpt + lay.n_seg); }
   char* second(char* slotp) { return slotp + lay.state_bytes; }
   int* flags() const { return (int*)small(lay.o_flags); }
@@ -706,6 +711,10 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
     } else if (mode == 2) {
       src = q == 0 ? nullptr : p->work();
       dst = q == np - 1 ? nullptr : p->work();
+    } else if (p->lay.rebuild) {
+      // in place in one slot; the last pass's output stays there for the backward sweep
+      src = q == 0 ? nullptr : p->rebuilt();
+      dst = p->rebuilt();
     } else {
       const int j = seg_of[q];
       const int s0 = p->seg[j].first, s1 = p->seg[j].second;
@@ -725,8 +734,12 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
     double b_set = 0, b_clear = 0;
     int flag = -1;
     if (mode != 0 && q == np - 1) {
-      // the backward sweep from pass outputs starts from the final states (kept in the working slot)
-      if (mode == 1) {
+      // the backward sweep from pass outputs starts from the final states (kept in the working slot,
+      // or in the rebuilt slot, where they are always stored)
+      if (mode == 1 && p->lay.rebuild) {
+        a.dst_psi = dst;
+        a.dst_dpsi = p->second(dst);
+      } else if (mode == 1) {
         a.dst_psi = p->work();
         a.dst_dpsi = p->second(p->work());
         a.store_if = p->flags() + qhvp::kFlagInverse;
@@ -734,12 +747,12 @@ qhvp_status forward_sweep(qhvp_problem* p, const std::vector<qhvp::PassDesc>& pa
       }
       a.phi0 = p->phi0();
       a.ov_part = ovpart;
-      b_clear = (src ? nst * S : 0) + S;
-      b_set = b_clear + (mode == 1 ? nst * S : 0);
+      b_clear = (src ? nst * S : 0) + S + (p->lay.rebuild && mode == 1 ? nst * S : 0);
+      b_set = (src ? nst * S : 0) + S + (mode == 1 ? nst * S : 0);
     } else {
       a.dst_psi = dst;
       a.dst_dpsi = p->second(dst);
-      if (mode == 1 && dst_kept) {
+      if (mode == 1 && dst_kept && !p->lay.rebuild) {
         a.psi_skip = p->flags() + qhvp::kFlagKeep;
         flag = qhvp::kFlagKeep;
       }
@@ -816,23 +829,40 @@ qhvp_status backward_sweep(qhvp_problem* p, int tangent) {
       b.store_ab = (q > 0);
       b.env_part = envpart;
       b.run_flag = finv;
-      // forward states: the pass input (recomputing kernel) or the pass output (inverse kernel)
-      char* src_in = q == s0 ? start : p->segbuf(q - s0);
-      char* src_out = q + 1 < s1 ? p->segbuf(q + 1 - s0) : (j == J - 1 ? ab : p->ckpt(j + 1));
-      qhvp::BwdArgs bo = b, br = b;
-      bo.src_psi = src_out;
-      bo.src_dpsi = p->second(src_out);
-      bo.run_when = 1;
-      br.src_psi = src_in;
-      br.src_dpsi = src_in ? p->second(src_in) : nullptr;
-      br.run_when = 0;
       const double S = state_bytes_alg(p), nst = tangent ? 2 : 1;
       const double common = (b.fold ? S : nst * S) + (b.store_ab ? nst * S : 0);
-      HIP_TRY(prof_begin(p));
-      LAUNCH_TRY(qhvp::launch_bwd_out(p->dprec(), bo, p->stream));
-      LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), br, p->stream));
-      HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, common + nst * S, pass_flops(p, b.pd, tangent, true), qhvp::kFlagInverse,
-                       common + (src_in ? nst * S : 0)));
+      if (p->lay.rebuild) {
+        // from the pass output, rebuilding the pass input in place for the next backward pass (the
+        // first pass's input is not needed); k_prep has checked that every gate can be undone
+        qhvp::BwdArgs bo = b;
+        bo.src_psi = p->rebuilt();
+        bo.src_dpsi = p->second(p->rebuilt());
+        if (q > 0) {
+          bo.dst_psi = p->rebuilt();
+          bo.dst_dpsi = p->second(p->rebuilt());
+        }
+        bo.run_when = 1;
+        HIP_TRY(prof_begin(p));
+        LAUNCH_TRY(qhvp::launch_bwd_out(p->dprec(), bo, p->stream));
+        HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, common + nst * S + (q > 0 ? nst * S : 0),
+                         pass_flops(p, b.pd, tangent, true)));
+      } else {
+        // forward states: the pass input (recomputing kernel) or the pass output (inverse kernel)
+        char* src_in = q == s0 ? start : p->segbuf(q - s0);
+        char* src_out = q + 1 < s1 ? p->segbuf(q + 1 - s0) : (j == J - 1 ? ab : p->ckpt(j + 1));
+        qhvp::BwdArgs bo = b, br = b;
+        bo.src_psi = src_out;
+        bo.src_dpsi = p->second(src_out);
+        bo.run_when = 1;
+        br.src_psi = src_in;
+        br.src_dpsi = src_in ? p->second(src_in) : nullptr;
+        br.run_when = 0;
+        HIP_TRY(prof_begin(p));
+        LAUNCH_TRY(qhvp::launch_bwd_out(p->dprec(), bo, p->stream));
+        LAUNCH_TRY(qhvp::launch_bwd(p->dprec(), br, p->stream));
+        HIP_TRY(prof_end(p, QHVP_KERNEL_BACKWARD, common + nst * S, pass_flops(p, b.pd, tangent, true),
+                         qhvp::kFlagInverse, common + (src_in ? nst * S : 0)));
+      }
       const long long items = (long long)p->Ns << (p->n - b.pd.mb);
       const int nwg_out = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, items, 1);
       const int nwg_rec = qhvp::bwd_grid(p->dprec(), tangent, b.pd.ng, items, 0);
@@ -879,8 +909,9 @@ qhvp_status core_forward(qhvp_problem* p, const double* d_G, const double* d_V, 
   pa.prec = p->dprec();
   pa.tangent = tangent;
   pa.riem = mode != 0 ? riem : 0;
-  pa.with_inverse = (mode != 0 && !env_recompute()) ? 1 : 0;
-  pa.keep_mode = mode != 0 ? 1 : 0;
+  pa.rebuild = (mode != 0 && p->lay.rebuild) ? 1 : 0;
+  pa.with_inverse = (mode != 0 && (pa.rebuild || !env_recompute())) ? 1 : 0;
+  pa.keep_mode = (mode != 0 && !p->lay.rebuild) ? 1 : 0;   // rebuilding overwrites the forward states
   pa.invalidate_kept = p->invalidate_kept;
   pa.G_in = d_G;
   pa.V_in = tangent ? d_V : nullptr;

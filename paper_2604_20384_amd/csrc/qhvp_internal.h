@@ -98,6 +98,10 @@ struct BwdArgs {
   // backward kernels of a pass and the device-side choice (kFlagInverse) picks one
   const int* run_flag;
   int run_when;
+  // launch_bwd_out only: if not null, the forward states at the pass INPUT, which the kernel rebuilds
+  // by undoing every gate of the pass, are stored here (may equal src_*: a tile writes only the
+  // amplitudes it read)
+  void* dst_psi; void* dst_dpsi;
 };
 
 // Upper bound of the workgroup count of any pass kernel over `items` tiles (sizes per-workgroup
@@ -131,9 +135,14 @@ constexpr int kFlagKeep = 3;       // this sweep's gates equal kept_g bitwise: s
 constexpr int kFlagCount = 8;
 constexpr int kStatNonFinite = 1;  // a non-finite entry in G or V
 constexpr int kStatNotUnitary = 2; // Riemannian geometry with |G^dag G - I|_F > 1e-10 for some gate
+constexpr int kStatNotInvertible = 4;   // the rebuilding backward sweep with a gate beyond kRebuildCond
 // The backward sweep undoes gates on pass outputs only if every gate has |G|_F |G^-1|_F <= this (4 for a
 // unitary gate), so that undoing the at most kMaxGates gates of a pass loses at most a few bits.
 constexpr double kInverseCond = 8.0;
+// The backward sweep that rebuilds every pass boundary undoes all K gates in a row, so their
+// rounding errors add up over the circuit instead of over one pass: it needs every gate to be a
+// unitary up to a scale to about 1e-6 (|G|_F |G^-1|_F >= 4, with equality exactly for those).
+constexpr double kRebuildCond = 4.0 * (1.0 + 1e-6);
 
 // Prepare a call's gates: G_in, V_in (K*16 complex FP64, device) -> device precision gates / dirs
 // (V projected onto the tangent space at G when riem), FP64 copies g64 / v64, and, when with_inverse,
@@ -142,6 +151,7 @@ constexpr double kInverseCond = 8.0;
 // and G_in == kept_g bitwise (and !invalidate_kept); then kept_g = G_in.
 struct PrepArgs {
   int K, prec, tangent, riem, with_inverse, keep_mode, invalidate_kept;
+  int rebuild;   // the backward sweep rebuilds the pass boundaries: kRebuildCond or kStatNotInvertible
   const double* G_in;
   const double* V_in;
   void* gates;

@@ -1305,6 +1305,9 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
   const T* srcD = (const T*)a.src_dpsi;
   T* abA = (T*)a.ab_a;
   T* abB = (T*)a.ab_b;
+  T* dstP = (T*)a.dst_psi;
+  T* dstD = (T*)a.dst_dpsi;
+  const bool store_x = dstP != nullptr;   // the first gate is undone too, and the pass input stored
   const T* __restrict__ phi0 = (const T*)a.phi0;
   const unsigned imask = (unsigned)pd.imask;
   const bool wl = pd.wave_local != 0;
@@ -1461,7 +1464,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       {
         const GateOff O = gate_offsets_raw(rw[(MAXG - 1) & 1].off);
         env_reads(rw[(MAXG - 1) & 1], O);
-        w_reads(rw[(MAXG - 1) & 1], O, MAXG > 1 || a.store_ab, MAXG > 1);
+        w_reads(rw[(MAXG - 1) & 1], O, MAXG > 1 || a.store_ab, MAXG > 1 || store_x);
       }
 #pragma unroll
       for (int j = MAXG - 1; j >= 0; --j) {
@@ -1472,7 +1475,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
           wy.mfma(cur.op[0], cur.op[1]);
           wy.store(sY, sY + TSP, ad);
         }
-        if (j > 0) {
+        if (j > 0 || store_x) {
           wx.mfma(cur.op[2], cur.op[3]);
           wx.store(sX, sX + TSP, ad);
         }
@@ -1482,7 +1485,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
         GateOff On{};   // gate j-1's offsets
         if (j > 0) {
           On = gate_offsets_raw(rw[(j + 1) & 1].off);
-          w_reads(rw[(j + 1) & 1], On, j > 1 || a.store_ab, j > 1);
+          w_reads(rw[(j + 1) & 1], On, j > 1 || a.store_ab, j > 1 || store_x);
         }
         pin16(av);
         pin16(bx);
@@ -1540,7 +1543,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) { sY[ix[i]] = pa[i]; if (TANG) sY[TSP + ix[i]] = pb[i]; }
           }
-          if (j > 0) {
+          if (j > 0 || store_x) {
             T p[4], d[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) { p[i] = sX[ix[i]]; if (TANG) d[i] = sX[TSP + ix[i]]; }
@@ -1559,6 +1562,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
       IO::read(st0, sY, tid);
       if (TANG) IO::read(st1, sY + TSP, tid);
       st_base = base;
+    }
+    if (store_x) {   // the rebuilt pass-input forward states, over the pass-output states this tile read
+      IO::store(dstP, sX, base, xv, TS, tid);
+      if (TANG) IO::store(dstD, sX + TSP, base, xv, TS, tid);
     }
     __syncthreads();
     s = sn;

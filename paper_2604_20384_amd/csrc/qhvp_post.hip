@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(kPostThreads) k_prep(PrepArgs a) {
     store4(G, a.g64 + 32 * (size_t)k);
     store4(V, a.v64 + 32 * (size_t)k);
     if (a.with_inverse) {
-      const bool ok = inv4(G, Gi, tmp) && fro4(G) * fro4(Gi) <= kInverseCond;
+      const bool ok = inv4(G, Gi, tmp) && fro4(G) * fro4(Gi) <= (a.rebuild ? kRebuildCond : kInverseCond);
       if (ok) {
         zd *t = tmp + 32, *Y = tmp + 48;
         mm4(Gi, V, t);
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kPostThreads) k_prep(PrepArgs a) {
   }
   if (tid == 0) {
     a.flags[kFlagInverse] = (a.with_inverse && all_inv) ? 1 : 0;
-    a.flags[kFlagStatus] = any_bad ? sBad : 0;
+    a.flags[kFlagStatus] = (any_bad ? sBad : 0) | ((a.rebuild && !all_inv) ? kStatNotInvertible : 0);
     if (a.keep_mode) {
       a.flags[kFlagKeep] = (!a.invalidate_kept && a.flags[kFlagKeptValid] && all_same) ? 1 : 0;
       a.flags[kFlagKeptValid] = any_bad ? 0 : 1;

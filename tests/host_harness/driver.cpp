@@ -74,8 +74,12 @@ static void plans() {
       for (int s : seen) CHECK(s == 1);
       CHECK(qhvp_plan(n, L, np - 1, per.data(), nullptr) < 0);   // too small a buffer
       for (int prec : {0, 1})
-        for (int ck : {0, 1, 2, 4, -2})
+        for (int ck : {0, 1, 2, 4, -2, QHVP_CKPT_REBUILD})
           CHECK(qhvp_workspace_bytes(n, L, 2 * L, 3, (qhvp_precision)prec, ck, 1) > 0);
+      // rebuilding keeps two slots of states, keeping every boundary one per pass
+      if (np >= 2)
+        CHECK(qhvp_workspace_bytes(n, L, 2 * L, 3, QHVP_C64_ACC64, QHVP_CKPT_REBUILD, 1) <=
+              qhvp_workspace_bytes(n, L, 2 * L, 3, QHVP_C64_ACC64, 0, 1));
     }
   CHECK(qhvp_plan(1, 3, 0, nullptr, nullptr) < 0 && qhvp_plan(31, 3, 0, nullptr, nullptr) < 0);
   CHECK(qhvp_workspace_bytes(1, 3, 6, 3, QHVP_C64_ACC64, 0, 1) == 0);
@@ -152,7 +156,7 @@ static void call_sequences() {
   CHECK(qhvp_ctx_create(0, &ctx) == QHVP_OK);
   const long live0 = stub_live_blocks();
   for (int prec : {0, 1})
-    for (int ck : {0, 1, -2}) {
+    for (int ck : {0, 1, -2, QHVP_CKPT_REBUILD}) {
       const int n = 7, L = 5, Lr = 10, ns = 4;
       const int K = qhvp_num_gates(n, L);
       auto uref = random_gates(qhvp_num_gates(n, Lr), true);

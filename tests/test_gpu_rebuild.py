@@ -1,0 +1,144 @@
+"""The backward sweep that rebuilds the pass boundaries (ckpt_every = "rebuild").
+
+Only the final forward states are kept.  Each backward pass undoes all its gates, which Eq. fis /
+Eq. dfis give when solved for the input states, and stores the pass input for the next backward
+pass.  So the rounding of the undo steps accumulates over the whole circuit, not over one pass.
+
+* Against the oracle: shapes whose pass plans cover every complex64 gate-count instance, and
+  complex128; Euclidean and Riemannian gradient and HVP; at the parity bars.
+* At n=20, L=20, N_s=256, complex64 rebuilt against an all-complex128 run that keeps boundaries,
+  globally and gate by gate (1e-5): the long undo chain stays within the complex64 bar.  Also
+  against the complex64 run that keeps every boundary, and the rebuilt run's peak HBM.
+* Two-phase calls and several directions at one G give the one-shot results bit for bit.
+* Gates that are not unitary up to a scale: gradient and HVP calls fail on the device and leave the
+  outputs untouched; cost calls still run.
+"""
+import numpy as np
+import pytest
+
+from oracle import circuit, riem, sv
+from parity import assert_close, assert_fidelity
+from paper_2604_20384_amd.api import plan
+from paper_2604_20384_amd.inputs import make_problem
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c128": 1e-10, "c64": 1e-5}
+CASES = [  # (n, L, N_s, gate counts the plan must contain)
+    (2, 5, 3, {3}), (6, 3, 3, {2, 6}), (13, 11, 2, {1, 5, 6}), (13, 3, 2, {2, 4, 6}), (12, 7, 2, {3, 6}),
+]
+
+
+def _gp(p, precision, ckpt="rebuild", ns=None):
+    from paper_2604_20384_amd.api import Problem
+    samples = p.samples if ns is None else p.samples[:ns]
+    return Problem(p.n, p.L, p.uref, samples, L_ref=p.L_ref, precision=precision, ckpt_every=ckpt)
+
+
+@pytest.mark.parametrize("n,L,ns,counts", CASES)
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_rebuild_against_oracle(gpu, n, L, ns, counts, precision):
+    per, _ = plan(n, L)
+    assert counts <= set(per), (n, L, per)
+    p = make_problem(n, L, ns, seed=80 + n + L)
+    psi, phi = circuit.labels(p.uref, p.samples, n, p.L_ref)
+    ref = sv.evaluate(psi, phi, p.G, p.V, n, L)
+    tol = TOL[precision]
+    gp = _gp(p, precision)
+    c, g, h = gp.hvp(p.G, p.V)
+    assert_fidelity(gp.last_fidelity, ref["fidelity"], tol, (n, L, precision))
+    assert_close(g, ref["grad"], tol, (n, L, precision, "grad"))
+    assert_close(h, ref["hvp"], tol, (n, L, precision, "hvp"))
+    cR, gR, hR = gp.hvp(p.G, p.V, riemannian=True)
+    Vt = riem.project(p.G, p.V)
+    assert_close(gR, riem.riemannian_grad(p.G, ref["grad"]), tol, (n, L, precision, "Riemannian grad"))
+    refR = sv.evaluate(psi, phi, p.G, Vt, n, L)
+    assert_close(hR, riem.riemannian_hvp(p.G, refR["grad"], refR["hvp"], Vt), tol, (n, L, precision, "Riemannian hvp"))
+    c2, g2 = gp.grad(p.G)
+    assert_close(g2, ref["grad"], tol, (n, L, precision, "grad call"))
+    gp.close()
+
+
+def test_rebuild_headline_size(gpu):
+    import torch
+    p = make_problem(20, 20, 256, seed=1)
+    out = {}
+    for key, precision, ckpt in (("rebuild", "c64", "rebuild"), ("keep", "c64", 0), ("c128", "c128", -2)):
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        gp = _gp(p, precision, ckpt)
+        c, g, h = gp.hvp(p.G, p.V)
+        out[key] = (gp.last_fidelity, g, h, (torch.cuda.max_memory_allocated() - base) / 2 ** 30)
+        gp.close()
+        del gp
+    F4, g4, h4, mem = out["rebuild"]
+    F8, g8, h8, _ = out["c128"]
+    eF = assert_fidelity(F4, F8, 1e-5, "rebuild c64 vs c128")
+    eg = assert_close(g4, g8, 1e-5, "rebuild c64 vs c128 grad")
+    eh = assert_close(h4, h8, 1e-5, "rebuild c64 vs c128 hvp")
+    Fk, gk, hk, memk = out["keep"]
+    ek = assert_close(h4, hk, 1e-5, "rebuild vs keeping every boundary, c64 hvp")
+    print(f"n=20 L=20 N_s=256 c64 rebuilt vs c128: F {eF:.2e} grad {eg[0]:.2e} (per gate {eg[1]:.2e}) "
+          f"hvp {eh[0]:.2e} (per gate {eh[1]:.2e}); vs c64 keeping boundaries: hvp {ek[0]:.2e}; "
+          f"peak HBM {mem:.1f} GiB against {memk:.1f} GiB")
+    assert mem < 12.0
+
+
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_rebuild_two_phase_and_directions(gpu, precision):
+    p = make_problem(11, 6, 3, seed=91)
+    gp = _gp(p, precision)
+    c, g, h = gp.hvp(p.G, p.V)
+    gp.forward(p.G, p.V)
+    g2, h2 = gp.backward()
+    assert np.array_equal(g, g2) and np.array_equal(h, h2)
+    rng = np.random.default_rng(5)
+    Vs = np.stack([p.V, p.G @ (rng.standard_normal(p.G.shape) + 1j * rng.standard_normal(p.G.shape))])
+    cb, gb, hb = gp.hvp_batch(p.G, Vs)
+    for m in range(2):
+        _, _, hm = gp.hvp(p.G, Vs[m])
+        assert np.array_equal(hb[m], hm)
+    assert not gp.states_kept_for(p.G)
+    gp.close()
+
+
+def test_rebuild_rejects_gates_far_from_unitary(gpu):
+    import ctypes as C
+
+    import torch
+
+    from paper_2604_20384_amd import _lib
+    from paper_2604_20384_amd._lib import dptr, lib
+    p = make_problem(8, 4, 3, seed=93)
+    gp = _gp(p, "c64")
+    rng = np.random.default_rng(3)
+    Gb = p.G + 1e-3 * (rng.standard_normal(p.G.shape) + 1j * rng.standard_normal(p.G.shape))
+    Gf = np.ascontiguousarray(Gb).view(np.float64)
+    Vf = np.ascontiguousarray(p.V).view(np.float64)
+    cost, fid = np.full(1, 7.5), np.full(1, 7.5)
+    grad, hvp = np.full(Gf.shape, 7.5), np.full(Gf.shape, 7.5)
+    st = lib.qhvp_hvp(gp.handle, dptr(Gf), dptr(Vf), 0, dptr(cost), dptr(fid), dptr(grad), dptr(hvp))
+    assert st == _lib.QHVP_ERR_INVALID
+    assert gp.device_status() == _lib.QHVP_DEV_NOT_INVERTIBLE
+    assert np.all(cost == 7.5) and np.all(fid == 7.5) and np.all(grad == 7.5) and np.all(hvp == 7.5)
+    # the device-pointer form: enqueued, rejected on the device, outputs untouched
+    dG = torch.tensor(Gb, dtype=torch.complex128, device="cuda")
+    dV = torch.tensor(p.V, dtype=torch.complex128, device="cuda")
+    s = torch.full((2,), 7.5, dtype=torch.float64, device="cuda")
+    o = torch.full((p.K, 4, 4), 7.5, dtype=torch.complex128, device="cuda")
+    st = lib.qhvp_hvp_dev(gp.handle, dG.data_ptr(), dV.data_ptr(), 0, s.data_ptr(), s.data_ptr() + 8,
+                          C.c_void_p(None), o.data_ptr())
+    assert st == _lib.QHVP_OK and gp.device_status() == _lib.QHVP_DEV_NOT_INVERTIBLE
+    torch.cuda.synchronize()
+    assert bool(torch.all(s == 7.5)) and bool(torch.all(o == 7.5))
+    # cost calls need no inverse; gates unitary up to a scale (and to 1e-9) are accepted
+    c, F = gp.cost(Gb)
+    assert np.isfinite(c) and gp.device_status() == 0
+    psi, phi = circuit.labels(p.uref, p.samples, p.n, p.L_ref)
+    Gs = 1.5 * p.G
+    ref = sv.evaluate(psi, phi, Gs, p.V, p.n, p.L)
+    c, g, h = gp.hvp(Gs, p.V)
+    assert gp.device_status() == 0
+    assert_close(h, ref["hvp"], 1e-5, "scaled unitary gates")
+    gp.close()
