@@ -111,10 +111,12 @@ void qhvp_ctx_destroy(qhvp_ctx* ctx);
  *   ckpt_every = QHVP_CKPT_REBUILD : keep only the final forward states; the backward sweep
  *                    rebuilds every pass boundary from the one after it by undoing the pass's
  *                    gates (Eq. fis / Eq. dfis solved for the input states), so no boundary is
- *                    stored and none is recomputed: the speed of ckpt_every = 0 in the memory of
- *                    five state sets.  It needs gates that are unitary up to a scale to about
- *                    1e-6 (|G|_F |G^-1|_F <= 4 (1 + 1e-6)); gradient and HVP calls with other gates
- *                    fail on the device (QHVP_DEV_NOT_INVERTIBLE) and leave their outputs untouched.
+ *                    stored and none is recomputed: close to the speed of ckpt_every = 0 in the
+ *                    memory of five state sets.  The undo errors add up over all K gates, so it
+ *                    needs well-conditioned gates: |G|_F |G^-1|_F <= 4 (1 + 1e-6) for every gate
+ *                    (4 exactly for a unitary up to a scale; the bound admits singular values that
+ *                    differ by about 1e-3).  Gradient and HVP calls with other gates fail on the
+ *                    device (QHVP_DEV_NOT_INVERTIBLE) and leave their outputs untouched.
  *   with_tangent   : 1 to allow qhvp_hvp (stores the tangent states too).
  * Returns 0 on invalid arguments.
  */

@@ -98,7 +98,7 @@ class Problem:
     precision   : "c128" or "c64" (complex64 states, FP64 accumulation).
     ckpt_every  : layer-checkpoint interval (0 = keep every pass boundary, c > 0 every c layers,
                   -c every c passes), or "rebuild": keep only the final forward states and let the
-                  backward sweep rebuild the pass boundaries (gates unitary up to a scale).
+                  backward sweep rebuild the pass boundaries (well-conditioned gates).
     workspace   : "torch" (allocate with torch), a (device pointer, bytes) block owned by the
                   caller, or None (the library allocates).
     """

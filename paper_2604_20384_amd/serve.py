@@ -25,8 +25,23 @@ from concurrent.futures import Future
 
 import numpy as np
 
-# checkpoint policies from fastest (most memory) to leanest
-CKPT_CHOICES = (0, -2, 1, 2, 4, 8)
+# checkpoint policies from fastest (most memory) to leanest; "rebuild" (only the final forward
+# states kept, the backward sweep rebuilds the pass boundaries) needs well-conditioned gates
+CKPT_CHOICES = (0, "rebuild", -2, 1, 2, 4, 8)
+# The device accepts "rebuild" for gates with |G|_F |G^-1|_F <= 4 (1 + 1e-6); the planner asks for a
+# little less, so that no rounding difference between the two checks can make a planned request fail.
+REBUILD_COND = 4.0 * (1.0 + 0.5e-6)
+
+
+def rebuild_allowed(G: np.ndarray) -> bool:
+    """Whether every gate is conditioned well enough for the rebuilding sweep (the device's test)."""
+    G = np.asarray(G, dtype=np.complex128)
+    try:
+        Gi = np.linalg.inv(G)
+    except np.linalg.LinAlgError:
+        return False
+    prod = np.linalg.norm(G, axis=(1, 2)) * np.linalg.norm(Gi, axis=(1, 2))
+    return bool(np.all(prod <= REBUILD_COND))
 
 
 @dataclasses.dataclass
@@ -50,7 +65,7 @@ class Request:
 
 @dataclasses.dataclass
 class Plan:
-    ckpt_every: int
+    ckpt_every: int | str          # a checkpoint interval, or "rebuild"
     chunks: list                   # list of (start, stop) sample ranges
     bytes: int                     # device memory held while the request runs (largest chunk)
 
@@ -74,14 +89,15 @@ class Result:
 
 def plan_request(req: Request, bytes_fn, cap: int) -> Plan:
     """Fastest checkpoint policy whose workspace fits `cap`; split the samples in 2, 4, ...
-    chunks if none does.  Depends on the request's shape only."""
+    chunks if none does.  Depends on the request only (its shape, and its gates for "rebuild")."""
     Lr = req.L_ref if req.L_ref is not None else 2 * req.L
     ns = req.n_samples
     tangent = req.kind == "hvp"
+    choices = [ck for ck in CKPT_CHOICES if ck != "rebuild" or rebuild_allowed(req.G)]
     chunks = 1
     while True:
         size = math.ceil(ns / chunks)
-        for ck in CKPT_CHOICES:
+        for ck in choices:
             b = bytes_fn(req.n, req.L, Lr, size, req.precision, ck, tangent)
             if 0 < b <= cap:
                 rng = [(i, min(ns, i + size)) for i in range(0, ns, size)]

@@ -10,8 +10,8 @@ pass.  So the rounding of the undo steps accumulates over the whole circuit, not
   globally and gate by gate (1e-5): the long undo chain stays within the complex64 bar.  Also
   against the complex64 run that keeps every boundary, and the rebuilt run's peak HBM.
 * Two-phase calls and several directions at one G give the one-shot results bit for bit.
-* Gates that are not unitary up to a scale: gradient and HVP calls fail on the device and leave the
-  outputs untouched; cost calls still run.
+* Gates conditioned worse than the device accepts: gradient and HVP calls fail on the device and
+  leave the outputs untouched; cost calls still run.
 """
 import numpy as np
 import pytest
@@ -132,7 +132,7 @@ def test_rebuild_rejects_gates_far_from_unitary(gpu):
     assert st == _lib.QHVP_OK and gp.device_status() == _lib.QHVP_DEV_NOT_INVERTIBLE
     torch.cuda.synchronize()
     assert bool(torch.all(s == 7.5)) and bool(torch.all(o == 7.5))
-    # cost calls need no inverse; gates unitary up to a scale (and to 1e-9) are accepted
+    # cost calls need no inverse; unitaries up to a scale are accepted
     c, F = gp.cost(Gb)
     assert np.isfinite(c) and gp.device_status() == 0
     psi, phi = circuit.labels(p.uref, p.samples, p.n, p.L_ref)

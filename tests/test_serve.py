@@ -188,7 +188,7 @@ def test_gpu_chunked_request_against_oracle(gpu, precision, tol):
     q = serve.Request("hvp", 10, 4, p.uref, p.samples, p.G, p.V, L_ref=p.L_ref, precision=precision)
     cap = workspace_bytes(10, 4, 8, 3, precision, 0, True)
     plan = serve.plan_request(q, workspace_bytes, cap)
-    assert len(plan.chunks) >= 3, plan
+    assert len(plan.chunks) >= 2, plan
     srv = serve.Server(serve.GpuExecutor(), slots=2, memory_budget=4 * cap, request_cap=cap)
     r = srv.submit(q).result()
     srv.shutdown()
