@@ -219,7 +219,8 @@ qhvp_status qhvp_device_status(qhvp_problem* p, int* status);
  * 0, the segment checkpoints otherwise) are tagged with the gates G that produced them.  A later
  * gradient or HVP call whose G is bitwise the same reads them there and stores only the tangent
  * states over them; its results are identical to those of a call that rewrites them.  Any gradient
- * or HVP call at another G retags them; qhvp_cost never touches them.
+ * or HVP call at another G retags them; qhvp_cost never touches them.  With QHVP_CKPT_REBUILD
+ * nothing is kept (the backward sweep overwrites the forward states), so every call recomputes them.
  * qhvp_hvp_batch evaluates n_dirs HVPs at one G: V and hvp hold n_dirs*K*16 complex (direction m at
  * offset m*K*16), processed one tangent sweep pair after another; hvp[m] equals qhvp_hvp(G, V[m])
  * bit for bit.  cost and grad (the gradient at G) may be NULL.  All directions are validated before

@@ -101,6 +101,27 @@ def test_sample_chunking_matches_unchunked():
     assert np.allclose(r.grad, out["grad"], atol=1e-15) and np.allclose(r.hvp, out["hvp"], atol=1e-15)
 
 
+def test_planner_takes_the_rebuilding_sweep_when_boundaries_do_not_fit():
+    """Keeping every boundary when it fits the cap; else the rebuilding backward sweep if every gate
+    is conditioned well enough; else the recomputing checkpoint schedules."""
+    from paper_2604_20384_amd.api import workspace_bytes
+    q = _req(10, 8, 16, "hvp", 11)
+    keep = workspace_bytes(10, 8, 16, 16, "c128", 0, True)
+    rebuild = workspace_bytes(10, 8, 16, 16, "c128", "rebuild", True)
+    assert rebuild < keep
+    assert serve.plan_request(q, workspace_bytes, keep).ckpt_every == 0
+    p = serve.plan_request(q, workspace_bytes, rebuild)
+    assert p.ckpt_every == "rebuild" and p.chunks == [(0, 16)] and p.bytes == rebuild
+    G0 = q.G.copy()
+    # near a unitary the bound is second order: a 1e-5 perturbation still qualifies, 1e-3 does not
+    assert serve.rebuild_allowed(G0 + 1e-5)
+    rng = np.random.default_rng(0)
+    q.G = G0 + 1e-3 * (rng.standard_normal(G0.shape) + 1j * rng.standard_normal(G0.shape))
+    assert not serve.rebuild_allowed(q.G)
+    p = serve.plan_request(q, workspace_bytes, rebuild)
+    assert p.ckpt_every != "rebuild"
+
+
 def test_failure_is_isolated():
     ex = FakeExecutor(delay=0.01, fail_rid=2)
     srv = serve.Server(ex, slots=2, memory_budget=1 << 40)
