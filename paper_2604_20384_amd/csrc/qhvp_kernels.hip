@@ -1267,8 +1267,10 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 // which the host maps to the input-side sums (psi_in = G^-1 psi_out, dpsi_in = G^-1 (dpsi_out -
 // V psi_in)): E = Et G^-T and D = (Dt - E V^T) G^-T.  Each step runs three independent products
 // (environment, W^dag on (a, b), W^-1 on (psi, dpsi)).  igates holds G^-1 | Y per gate (32 complex).
+// complex128: two workgroups per CU (two waves per SIMD) need at most 256 registers per lane; left to
+// itself the compiler takes 268 for the 6-gate instance, and then one workgroup fits.
 template <typename R, bool TANG, int MAXG>
-__global__ void __launch_bounds__(kThreads) k_bwd_out(BwdArgs a) {
+__global__ void __launch_bounds__(kThreads, sizeof(R) == 8 ? 2 : 1) k_bwd_out(BwdArgs a) {
   using T = typename CT<R>::T;
   using M = Mfma<R>;
   using acc_t = typename M::acc_t;
