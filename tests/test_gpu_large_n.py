@@ -2,8 +2,8 @@
 and n = 24 through the per-sample overlaps the oracle computes one sample at a time.
 
 n = 21, 22: L = 6, 2 samples, complex128 (1e-10) and complex64 (1e-5), every pass boundary kept
-(ckpt 0) and layer checkpointing (ckpt 1), fidelity, gradient and HVP compared globally and gate by
-gate.  n = 24: L = 4, 2 samples, complex64; the oracle cannot cache every gate's state at this size,
+(ckpt 0), layer checkpointing (ckpt 1) and boundaries rebuilt by the backward sweep, fidelity,
+gradient and HVP compared globally and gate by gate.  n = 24: L = 4, 2 samples, complex64; the oracle cannot cache every gate's state at this size,
 so the sampled overlaps T_s = phi_s^dag G psi_s and the size-independent Euler identity are checked.
 """
 import numpy as np
@@ -28,7 +28,7 @@ def test_large_n_against_oracle(gpu, n):
     psi, phi = circuit.labels(p.uref, p.samples, n, p.L_ref)
     ref = sv.evaluate(psi, phi, p.G, p.V, n, L, batch=1)
     for precision in ("c128", "c64"):
-        for ckpt in (0, 1):
+        for ckpt in (0, 1, "rebuild"):
             torch.cuda.empty_cache()
             gp = Problem(n, L, p.uref, p.samples, L_ref=p.L_ref, precision=precision, ckpt_every=ckpt)
             c, g, h = gp.hvp(p.G, p.V)
