@@ -1268,7 +1268,7 @@ __global__ void __launch_bounds__(kThreads) k_bwd(BwdArgs a) {
 // V psi_in)): E = Et G^-T and D = (Dt - E V^T) G^-T.  Each step runs three independent products
 // (environment, W^dag on (a, b), W^-1 on (psi, dpsi)).  igates holds G^-1 | Y per gate (32 complex).
 // complex128: two workgroups per CU (two waves per SIMD) need at most 256 registers per lane; left to
-// itself the compiler takes 268 for the 6-gate instance, and then one workgroup fits.
+// itself the compiler took 268 for the 6-gate instance, and then one workgroup fits.
 template <typename R, bool TANG, int MAXG>
 __global__ void __launch_bounds__(kThreads, sizeof(R) == 8 ? 2 : 1) k_bwd_out(BwdArgs a) {
   using T = typename CT<R>::T;
@@ -1369,7 +1369,9 @@ __global__ void __launch_bounds__(kThreads, sizeof(R) == 8 ? 2 : 1) k_bwd_out(Bw
   const bool common = !a.fold;
   typename IO::V pfa[IO::NV], pfb[IO::NV], pfp[IO::NV], pfd[IO::NV];
   if (common && it0 < it1) QHVP_BWD_PREFETCH(s, x);
-  typename IO::V st0[IO::NV], st1[IO::NV];
+  // complex64 defers a tile's (a, b) stores until the next tile's loads are in; complex128 stores them
+  // straight from LDS (the registers of the deferred copy would not let two workgroups share a CU)
+  typename IO::V st0[kF32 ? IO::NV : 1], st1[kF32 ? IO::NV : 1];
   long long st_base = -1;
 
   const unsigned half = blockIdx.x >= gridDim.x / 2 ? 1u : 0u;
@@ -1408,9 +1410,11 @@ __global__ void __launch_bounds__(kThreads, sizeof(R) == 8 ? 2 : 1) k_bwd_out(Bw
       IO::load(sX, srcP, base, xv, TS, tid);
       if (TANG) IO::load(sX + TSP, srcD, base, xv, TS, tid);
     }
-    if (st_base >= 0) {
-      IO::write(abA, st0, st_base, xv, TS, tid);
-      if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+    if constexpr (kF32) {
+      if (st_base >= 0) {
+        IO::write(abA, st0, st_base, xv, TS, tid);
+        if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+      }
     }
     if constexpr (kF32) {
       // the staged partials of the previous pair of tiles (staged before the pair's final barrier;
@@ -1561,9 +1565,14 @@ __global__ void __launch_bounds__(kThreads, sizeof(R) == 8 ? 2 : 1) k_bwd_out(Bw
     }
 
     if (a.store_ab) {
-      IO::read(st0, sY, tid);
-      if (TANG) IO::read(st1, sY + TSP, tid);
-      st_base = base;
+      if constexpr (kF32) {
+        IO::read(st0, sY, tid);
+        if (TANG) IO::read(st1, sY + TSP, tid);
+        st_base = base;
+      } else {
+        IO::store(abA, sY, base, xv, TS, tid);
+        if (TANG) IO::store(abB, sY + TSP, base, xv, TS, tid);
+      }
     }
     if (store_x) {   // the rebuilt pass-input forward states, over the pass-output states this tile read
       IO::store(dstP, sX, base, xv, TS, tid);
@@ -1573,9 +1582,11 @@ __global__ void __launch_bounds__(kThreads, sizeof(R) == 8 ? 2 : 1) k_bwd_out(Bw
     s = sn;
     x = xn;
   }
-  if (st_base >= 0) {
-    IO::write(abA, st0, st_base, xv, TS, tid);
-    if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+  if constexpr (kF32) {
+    if (st_base >= 0) {
+      IO::write(abA, st0, st_base, xv, TS, tid);
+      if (TANG) IO::write(abB, st1, st_base, xv, TS, tid);
+    }
   }
   if constexpr (kF32) {
     if (it1 > it0) env_reduce<MAXG>(sStg, sAcc, tid);   // staged by the last one or two tiles, after their barrier
