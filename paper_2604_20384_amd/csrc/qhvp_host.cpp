@@ -191,15 +191,13 @@ std::vector<qhvp::PassDesc> plan_circuit(int n, int L, std::vector<int>* gates_b
   return passes;
 }
 
-// LDS index of tile element t in the kernels' layout: complex64 per-bit offsets (kLdsPadC64),
-// complex128 16 spare bytes after every 256 bytes.
+// LDS index of tile element t in the kernels' layout: per-bit offsets kLdsPadC64 (complex64) or
+// kLdsPadC128 (complex128).
 int lds_at(int t, int elem_bytes) {
-  if (elem_bytes == 8) {
-    int r = t;
-    for (int b = 5; b < qhvp::kMaxTileBits; ++b) r += ((t >> b) & 1) * qhvp::kLdsPadC64[b];
-    return r;
-  }
-  return t + (t >> 4);
+  const int* pad = elem_bytes == 8 ? qhvp::kLdsPadC64 : qhvp::kLdsPadC128;
+  int r = t;
+  for (int b = 0; b < qhvp::kMaxTileBits; ++b) r += ((t >> b) & 1) * pad[b];
+  return r;
 }
 
 // gfx950 LDS bank model, fitted to the hardware's bank-conflict counter on probe access patterns:
@@ -255,6 +253,35 @@ int c64_w_conflicts(const int* bits, int nbits, bool write) {
     w[l] = 8 * t;
   }
   return 16 * (lds_cycles(w, 8, write) - (write ? 4 : 2));
+}
+
+// Modelled bank-conflict cycles of complex128 gate steps for a gate on tile bits lo, hi.  Lane l
+// owns group l of the wave.  Its group reads and writes (128-bit, one per amplitude and state array:
+// 16 each in a backward step, 8 each in a forward step) are served 16 lanes (group bits 0..3) resp.
+// 8 lanes (bits 0..2) at a time, so their conflicts depend on the tile bits under those group bits
+// only (`bits`).  A backward step's environment operand reads (64-bit, 32 per step) run the lanes
+// over the state array, the real / imaginary part, the amplitude bits lo, hi and group bits 0, 1,
+// and are served 32 lanes (group bit 0, on tile bit p0) at a time.  Wave-uniform parts drop out.
+int c128_group_conflicts(const int* bits, int nbits, bool write) {
+  int g[64];
+  for (int l = 0; l < 64; ++l) {
+    int t = 0;
+    for (int i = 0; i < nbits; ++i)
+      if ((l >> i) & 1) t += lds_at(1 << bits[i], 16);
+    g[l] = 16 * t;
+  }
+  return lds_cycles(g, 16, write) - (write ? 8 : 4);
+}
+int c128_env_conflicts(int lo, int hi, int p0) {
+  auto O = [](int b) { return lds_at(1 << b, 16); };
+  int env[64];
+  for (int l = 0; l < 64; ++l) {
+    const int comp = l & 15, sub = l >> 4;
+    const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
+    const int tl = ((sub & 1) ? O(p0) : 0) + ((cidx & 1) ? O(lo) : 0) + ((cidx & 2) ? O(hi) : 0);
+    env[l] = 8 * (2 * (cst * qhvp::kTspC128 + tl) + cri);
+  }
+  return lds_cycles(env, 8, false) - 2;
 }
 
 // Per-pass constants of the kernels' tile addressing: the tile-enumeration mask and, per gate, the
@@ -325,6 +352,41 @@ void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
                   }
                 }
             }
+        }
+        if (elem_bytes == 16) {
+          // complex128: group bit 0 enters every access, bits 1, 2 the writes and the reads, bit 3
+          // the reads; weights: the backward step's 32 environment reads, 16 + 8 group reads and
+          // 16 + 8 group writes of a backward and a forward step
+          int env[6], wr[64], rd[64];
+          for (int e = 0; e < 6; ++e) env[e] = c128_env_conflicts(lo, hi, avail[e]);
+          for (int m = 0; m < 64; ++m) {
+            const int cnt = __builtin_popcount(m);
+            if (cnt != 3 && cnt != 4) continue;
+            int bits[4], r = 0;
+            for (int i = 0; i < 6; ++i)
+              if ((m >> i) & 1) bits[r++] = avail[i];
+            if (cnt == 3) wr[m] = c128_group_conflicts(bits, 3, true);
+            else rd[m] = c128_group_conflicts(bits, 4, false);
+          }
+          int best = -1;
+          for (int a0 = 0; a0 < 6; ++a0)
+            for (int a1 = 0; a1 < 6; ++a1)
+              for (int a2 = a1 + 1; a2 < 6; ++a2)
+                for (int a3 = 0; a3 < 6; ++a3) {
+                  if (a1 == a0 || a2 == a0 || a3 == a0 || a3 == a1 || a3 == a2) continue;
+                  const int m3 = (1 << a0) | (1 << a1) | (1 << a2), m4 = m3 | (1 << a3);
+                  const int c = 32 * env[a0] + 24 * wr[m3] + 24 * rd[m4];
+                  if (best < 0 || c < best) {
+                    best = c;
+                    pos[0] = avail[a0];
+                    pos[1] = avail[a1];
+                    pos[2] = avail[a2];
+                    pos[3] = avail[a3];
+                    int r = 4;
+                    for (int i = 0; i < 6; ++i)
+                      if (!((m4 >> i) & 1)) pos[r++] = avail[i];
+                  }
+                }
         }
         pos[6] = f0;
         pos[7] = f1;

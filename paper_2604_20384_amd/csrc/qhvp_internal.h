@@ -30,6 +30,20 @@ constexpr int kEnvVals = 64;      // 16 complex E + 16 complex D per gate, as 64
 constexpr int kLdsPadC64[kMaxTileBits] = {0, 0, 0, 0, 0, 2, 4, 8, 14, 40};
 constexpr int kTspC64 = 1093;
 
+// complex128 LDS tile layout (16-byte elements): tile bit b at element offset 2^b + kLdsPadC128[b] =
+// 1, 2, 4, 8, 17, 36, 72, 154, 296, 596 (one-to-one on the 1024 elements, extent 1187; index
+// kDummyC128 stays free), the second state array kTspC128 elements after the first.  Under the bank
+// model only the offsets modulo 16 elements (256 bytes) matter: 128-bit reads are served 16 lanes at
+// a time over 64 banks, 128-bit writes 8 lanes over 32 banks, and the 64-bit environment operand
+// reads 32 lanes over 64 banks.  The residues (1, 4, 8, 10, 8, 4 for bits 4..9, 5 for kTspC128) are
+// those with the fewest modelled conflict cycles of the forward and backward gate steps of the pass
+// plans at n = 12 .. 22, with the host's per-gate choice of lane bits; the multiples of 16 added
+// keep the layout one-to-one in the least extent.  Bits 0..3 stay unpadded: the tile transfers move
+// 16 consecutive elements per 16 lanes.
+constexpr int kLdsPadC128[kMaxTileBits] = {0, 0, 0, 0, 1, 4, 8, 26, 40, 84};
+constexpr int kTspC128 = 1189;
+constexpr int kDummyC128 = 16;
+
 struct PassDesc {
   int n;      // qubits
   int mb;     // tile bits

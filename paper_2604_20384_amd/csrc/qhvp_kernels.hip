@@ -180,14 +180,17 @@ template <> struct Lds<float2> {
     return r;
   }
 };
-// complex128: 16 spare bytes after every 256-byte row (+32 bytes so that the second state array
-// starts 8 banks over).
+// complex128: per-bit offsets chosen under the same bank model (kLdsPadC128).
 template <> struct Lds<double2> {
-  static constexpr int PS = 4;   // log2(elements per 256 B)
   static constexpr int TSMAX = 1 << kMaxTileBits;
-  static constexpr int TSP = TSMAX + (TSMAX >> PS) + 2;
-  static constexpr int DUMMY = 1 << PS;
-  static __device__ __forceinline__ int at(int t) { return t + (t >> PS); }
+  static constexpr int TSP = kTspC128;
+  static constexpr int DUMMY = kDummyC128;
+  static __device__ __forceinline__ int at(int t) {
+    int r = t;
+#pragma unroll
+    for (int b = 4; b < kMaxTileBits; ++b) r += ((t >> b) & 1) * kLdsPadC128[b];
+    return r;
+  }
 };
 
 // Global <-> LDS transfer of one state of a tile in 16-byte vectors: thread tid moves tile

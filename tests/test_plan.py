@@ -77,14 +77,15 @@ def test_plan_rejects_bad_shapes():
     assert _lib.lib.qhvp_plan(20, 20, 3, (_lib.C.c_int * 3)(), None) < 0
 
 
-def _header_constants():
-    """kLdsPadC64 / kTspC64 / kMaxTileBits as written in the kernels' shared header."""
+def _header_constants(prec="C64"):
+    """kLdsPad<prec> / kTsp<prec> / kMaxTileBits as written in the kernels' shared header."""
     import os
     import re
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     text = open(os.path.join(root, "paper_2604_20384_amd", "csrc", "qhvp_internal.h")).read()
-    pads = [int(x) for x in re.search(r"kLdsPadC64\[kMaxTileBits\]\s*=\s*\{([^}]*)\}", text).group(1).split(",")]
-    tsp = int(re.search(r"constexpr int kTspC64\s*=\s*(\d+);", text).group(1))
+    pads = [int(x) for x in
+            re.search(r"kLdsPad" + prec + r"\[kMaxTileBits\]\s*=\s*\{([^}]*)\}", text).group(1).split(",")]
+    tsp = int(re.search(r"constexpr int kTsp" + prec + r"\s*=\s*(\d+);", text).group(1))
     bits = int(re.search(r"constexpr int kMaxTileBits\s*=\s*(\d+);", text).group(1))
     return pads, tsp, bits
 
@@ -99,3 +100,22 @@ def test_complex64_lds_layout_is_one_to_one():
     assert len(set(at)) == len(at)
     assert max(at) < tsp
     assert 32 not in at
+
+
+def test_complex128_lds_layout_is_one_to_one():
+    """The padded complex128 tile layout: one slot per tile element below the second state array's
+    offset, bits 0..3 unpadded (16 lanes move 16 consecutive elements), the dummy slot free, and two
+    state arrays of both tile buffers of the backward kernel within half of the 160 KB of LDS, so
+    that two workgroups share a CU."""
+    import re
+    pads, tsp, bits = _header_constants("C128")
+    assert len(pads) == bits and pads[:4] == [0] * 4
+    at = [t + sum(pads[b] for b in range(bits) if t >> b & 1) for t in range(1 << bits)]
+    assert len(set(at)) == len(at)
+    assert max(at) < tsp
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    text = open(os.path.join(root, "paper_2604_20384_amd", "csrc", "qhvp_internal.h")).read()
+    dummy = int(re.search(r"constexpr int kDummyC128\s*=\s*(\d+);", text).group(1))
+    assert dummy not in at and dummy < tsp
+    assert 2 * 2 * tsp * 16 <= 80 * 1024 - 2048
