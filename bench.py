@@ -216,16 +216,23 @@ def cpu_info():
 
 # ---------------------------------------------------------------------------------------------
 
+def kernel_source_sha256():
+    """sha256 of the sweep kernels' source and the shared header that fixes their layouts."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("qhvp_kernels.hip", "qhvp_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2604_20384_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
 def measured_traffic(kernel_name):
     """HBM bytes per launch of `kernel_name` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary (scaled by the copy-kernel calibration), or None if the kernel source has changed
     since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, TRAFFIC_PROFILE)
-    src = os.path.join(ROOT, "paper_2604_20384_amd", "csrc", "qhvp_kernels.hip")
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        sha = kernel_source_sha256()
     except OSError:
         return None, None
     if rec.get("kernel") != kernel_name or not sha.startswith(rec["kernel_source_sha256_prefix"]):

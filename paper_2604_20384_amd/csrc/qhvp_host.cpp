@@ -205,6 +205,9 @@ int lds_at(int t, int elem_bytes) {
 // over 32 banks of 4 bytes; 64-bit reads: 32 lanes over 64 banks; 64-bit writes: 16 lanes over 32
 // banks; 128-bit reads: 16 lanes over 64 banks; 128-bit writes: 8 lanes over 32 banks), and a group
 // takes as many cycles as its most used bank holds distinct dwords.  Returns the wave's cycles.
+// 128-bit reads follow it only roughly (on the complex128 kernels' group patterns it is exact for
+// half of them and low by two cycles on average); a ds_read2st64_b64 is two 64-bit accesses, each
+// served 16 lanes at a time over 32 banks.
 int lds_cycles(const int (&addr)[64], int width, bool write) {
   int group = 32, banks = 32;
   if (width == 8) { group = write ? 16 : 32; banks = write ? 32 : 64; }
@@ -255,13 +258,11 @@ int c64_w_conflicts(const int* bits, int nbits, bool write) {
   return 16 * (lds_cycles(w, 8, write) - (write ? 4 : 2));
 }
 
-// Modelled bank-conflict cycles of complex128 gate steps for a gate on tile bits lo, hi.  Lane l
-// owns group l of the wave.  Its group reads and writes (128-bit, one per amplitude and state array:
-// 16 each in a backward step, 8 each in a forward step) are served 16 lanes (group bits 0..3) resp.
-// 8 lanes (bits 0..2) at a time, so their conflicts depend on the tile bits under those group bits
-// only (`bits`).  A backward step's environment operand reads (64-bit, 32 per step) run the lanes
-// over the state array, the real / imaginary part, the amplitude bits lo, hi and group bits 0, 1,
-// and are served 32 lanes (group bit 0, on tile bit p0) at a time.  Wave-uniform parts drop out.
+// Modelled bank-conflict cycles of a complex128 group read (`write` false: 128-bit, 16 lanes at a
+// time) or write (128-bit, 8 lanes at a time) whose lanes run over group bits 0..nbits-1 on tile bits
+// `bits`.  Lane l owns group l of the wave; the other lanes' addresses are a common shift of these.
+// (The environment operand reads of a backward step do not depend on this choice: their lanes run
+// over the amplitude bits of the gate, the state array and the real / imaginary part.)
 int c128_group_conflicts(const int* bits, int nbits, bool write) {
   int g[64];
   for (int l = 0; l < 64; ++l) {
@@ -271,17 +272,6 @@ int c128_group_conflicts(const int* bits, int nbits, bool write) {
     g[l] = 16 * t;
   }
   return lds_cycles(g, 16, write) - (write ? 8 : 4);
-}
-int c128_env_conflicts(int lo, int hi, int p0) {
-  auto O = [](int b) { return lds_at(1 << b, 16); };
-  int env[64];
-  for (int l = 0; l < 64; ++l) {
-    const int comp = l & 15, sub = l >> 4;
-    const int cst = comp >> 3, cri = (comp >> 2) & 1, cidx = comp & 3;
-    const int tl = ((sub & 1) ? O(p0) : 0) + ((cidx & 1) ? O(lo) : 0) + ((cidx & 2) ? O(hi) : 0);
-    env[l] = 8 * (2 * (cst * qhvp::kTspC128 + tl) + cri);
-  }
-  return lds_cycles(env, 8, false) - 2;
 }
 
 // Per-pass constants of the kernels' tile addressing: the tile-enumeration mask and, per gate, the
@@ -354,11 +344,9 @@ void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
             }
         }
         if (elem_bytes == 16) {
-          // complex128: group bit 0 enters every access, bits 1, 2 the writes and the reads, bit 3
-          // the reads; weights: the backward step's 32 environment reads, 16 + 8 group reads and
-          // 16 + 8 group writes of a backward and a forward step
-          int env[6], wr[64], rd[64];
-          for (int e = 0; e < 6; ++e) env[e] = c128_env_conflicts(lo, hi, avail[e]);
+          // complex128: group bits 0..2 serve the writes (8 lanes) and 0..3 the reads (16 lanes);
+          // a backward step issues 16 of each and a forward step 8, so both weigh the same
+          int wr[64], rd[64];
           for (int m = 0; m < 64; ++m) {
             const int cnt = __builtin_popcount(m);
             if (cnt != 3 && cnt != 4) continue;
@@ -369,24 +357,23 @@ void fill_tile_offsets(std::vector<qhvp::PassDesc>& passes, int elem_bytes) {
             else rd[m] = c128_group_conflicts(bits, 4, false);
           }
           int best = -1;
-          for (int a0 = 0; a0 < 6; ++a0)
-            for (int a1 = 0; a1 < 6; ++a1)
-              for (int a2 = a1 + 1; a2 < 6; ++a2)
-                for (int a3 = 0; a3 < 6; ++a3) {
-                  if (a1 == a0 || a2 == a0 || a3 == a0 || a3 == a1 || a3 == a2) continue;
-                  const int m3 = (1 << a0) | (1 << a1) | (1 << a2), m4 = m3 | (1 << a3);
-                  const int c = 32 * env[a0] + 24 * wr[m3] + 24 * rd[m4];
-                  if (best < 0 || c < best) {
-                    best = c;
-                    pos[0] = avail[a0];
-                    pos[1] = avail[a1];
-                    pos[2] = avail[a2];
-                    pos[3] = avail[a3];
-                    int r = 4;
-                    for (int i = 0; i < 6; ++i)
-                      if (!((m4 >> i) & 1)) pos[r++] = avail[i];
-                  }
-                }
+          for (int m3 = 0; m3 < 64; ++m3) {
+            if (__builtin_popcount(m3) != 3) continue;
+            for (int a3 = 0; a3 < 6; ++a3) {
+              if ((m3 >> a3) & 1) continue;
+              const int m4 = m3 | (1 << a3);
+              const int c = wr[m3] + rd[m4];
+              if (best < 0 || c < best) {
+                best = c;
+                int r = 0;
+                for (int i = 0; i < 6; ++i)
+                  if ((m3 >> i) & 1) pos[r++] = avail[i];
+                pos[r++] = avail[a3];
+                for (int i = 0; i < 6; ++i)
+                  if (!((m4 >> i) & 1)) pos[r++] = avail[i];
+              }
+            }
+          }
         }
         pos[6] = f0;
         pos[7] = f1;

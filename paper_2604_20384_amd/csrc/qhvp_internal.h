@@ -31,17 +31,20 @@ constexpr int kLdsPadC64[kMaxTileBits] = {0, 0, 0, 0, 0, 2, 4, 8, 14, 40};
 constexpr int kTspC64 = 1093;
 
 // complex128 LDS tile layout (16-byte elements): tile bit b at element offset 2^b + kLdsPadC128[b] =
-// 1, 2, 4, 8, 17, 36, 72, 154, 296, 596 (one-to-one on the 1024 elements, extent 1187; index
-// kDummyC128 stays free), the second state array kTspC128 elements after the first.  Under the bank
-// model only the offsets modulo 16 elements (256 bytes) matter: 128-bit reads are served 16 lanes at
-// a time over 64 banks, 128-bit writes 8 lanes over 32 banks, and the 64-bit environment operand
-// reads 32 lanes over 64 banks.  The residues (1, 4, 8, 10, 8, 4 for bits 4..9, 5 for kTspC128) are
-// those with the fewest modelled conflict cycles of the forward and backward gate steps of the pass
-// plans at n = 12 .. 22, with the host's per-gate choice of lane bits; the multiples of 16 added
-// keep the layout one-to-one in the least extent.  Bits 0..3 stay unpadded: the tile transfers move
-// 16 consecutive elements per 16 lanes.
-constexpr int kLdsPadC128[kMaxTileBits] = {0, 0, 0, 0, 1, 4, 8, 26, 40, 84};
-constexpr int kTspC128 = 1189;
+// 1, 2, 4, 8, 17, 40, 74, 148, 306, 604 (one-to-one on the 1024 elements, extent 1205; index
+// kDummyC128 stays free), the second state array kTspC128 elements after the first.  Only the
+// offsets modulo 16 elements (256 bytes) decide bank conflicts.  Measured on gfx950: 128-bit writes
+// are served 8 lanes at a time over 32 banks; the environment operand reads (ds_read2st64_b64) as
+// two 64-bit accesses, each 16 lanes at a time over 32 banks; 128-bit reads roughly 16 lanes at a
+// time over 64 banks.  The environment reads of a gate on tile bits lo, hi then depend only on the
+// residues of lo, hi and kTspC128; the group reads and writes on the tile bits the host puts under
+// the lanes.  The residues (1, 8, 10, 4, 2, 12 for bits 4..9, 5 for kTspC128) are those with the
+// fewest modelled conflict cycles of the forward and backward gate steps of the pass plans at
+// n = 12 .. 22 among layouts whose two tile buffers (four state arrays) leave two workgroups of the
+// backward kernel room on a CU; the multiples of 16 added keep the layout one-to-one.  Bits 0..3
+// stay unpadded: the tile transfers move 16 consecutive elements per 16 lanes.
+constexpr int kLdsPadC128[kMaxTileBits] = {0, 0, 0, 0, 1, 8, 10, 20, 50, 92};
+constexpr int kTspC128 = 1205;
 constexpr int kDummyC128 = 16;
 
 struct PassDesc {
