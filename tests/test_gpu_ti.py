@@ -2,7 +2,8 @@
 
 * Per-layer gradient and HVP against the oracle (oracle/ti.py: expand, evaluate per gate, sum),
   both precisions, Euclidean and Riemannian, for an even n, an odd n (both layer kinds full) and
-  n = 2, whose odd layers hold no gate (their derivatives are exactly zero).
+  n = 2, whose odd layers hold no gate (their derivatives are exactly zero); also with every pass
+  boundary kept and with the boundaries rebuilt by the backward sweep.
 * The device-side per-layer sums are exactly the sums, in increasing gate order, of the per-gate
   results of the same circuit expanded (bit for bit: the expansion copies the layer gates, and the
   per-gate evaluation is the one the per-gate calls run).
@@ -30,9 +31,9 @@ def _ti_case(n, L, ns, seed):
     return p, Gl, Vl
 
 
-def _problem(p, precision):
+def _problem(p, precision, ckpt=1):
     from paper_2604_20384_amd.api import Problem
-    return Problem(p.n, p.L, p.uref, p.samples, L_ref=p.L_ref, precision=precision, ckpt_every=1)
+    return Problem(p.n, p.L, p.uref, p.samples, L_ref=p.L_ref, precision=precision, ckpt_every=ckpt)
 
 
 def _t(a):
@@ -63,6 +64,22 @@ def test_ti_against_oracle(gpu, n, L, ns, precision):
     _close_layers(gR, riem.riemannian_grad(Gl, ref["grad"]), tol, "TI Riemannian grad", n, L)
     c3, gR3, hR = gp.hvp_ti(Gl, Vl, riemannian=True)
     _close_layers(hR, riem.riemannian_hvp(Gl, ref["grad"], ref["hvp"], Vl), tol, "TI Riemannian hvp", n, L)
+    gp.close()
+
+
+@pytest.mark.parametrize("ckpt", [0, "rebuild"])
+@pytest.mark.parametrize("precision", ["c128", "c64"])
+def test_ti_other_checkpoint_modes(gpu, precision, ckpt):
+    """Every pass boundary kept, and the boundaries rebuilt by the backward sweep: same bars."""
+    n, L = 11, 7
+    p, Gl, Vl = _ti_case(n, L, 3, 71)
+    tol = TOL[precision]
+    ref = ti.evaluate(p.uref, p.samples, Gl, Vl, n, L, p.L_ref)
+    gp = _problem(p, precision, ckpt)
+    c, g, h = gp.hvp_ti(Gl, Vl)
+    assert_fidelity(gp.last_fidelity, ref["fidelity"], tol, (precision, ckpt))
+    _close_layers(g, ref["grad"], tol, ("TI grad", ckpt), n, L)
+    _close_layers(h, ref["hvp"], tol, ("TI hvp", ckpt), n, L)
     gp.close()
 
 
