@@ -5,6 +5,9 @@ n = 21, 22: L = 6, 2 samples, complex128 (1e-10) and complex64 (1e-5), every pas
 (ckpt 0), layer checkpointing (ckpt 1) and boundaries rebuilt by the backward sweep, fidelity,
 gradient and HVP compared globally and gate by gate.  n = 24: L = 4, 2 samples, complex64; the oracle cannot cache every gate's state at this size,
 so the sampled overlaps T_s = phi_s^dag G psi_s and the size-independent Euler identity are checked.
+n = 30, the largest size the library takes (16 GiB per complex128 state): L = 2, one sample, both
+precisions with rebuilt boundaries; no oracle runs at this size, so complex64 is checked against
+complex128 (1e-5, globally and gate by gate) and complex128 against the Euler identity (1e-10).
 """
 import numpy as np
 import pytest
@@ -59,3 +62,30 @@ def test_n24_sampled_overlaps(gpu):
     assert abs(F - np.mean(np.abs(T) ** 2)) <= 1e-12 * F
     e = np.einsum("kij,kij->k", np.conj(g), p.G)
     assert np.max(np.abs(e + 2 * F)) <= 1e-5 * 2 * F
+
+
+def test_n30_maximum_size(gpu):
+    import torch
+
+    from paper_2604_20384_amd.api import Problem
+    n, L, ns = 30, 2, 1
+    free, _ = torch.cuda.mem_get_info()
+    if free < 120 * 2 ** 30:
+        pytest.skip("needs 120 GiB of free device memory")
+    p = make_problem(n, L, ns, seed=330)
+    out = {}
+    for precision in ("c128", "c64"):
+        torch.cuda.empty_cache()
+        gp = Problem(n, L, p.uref, p.samples, L_ref=p.L_ref, precision=precision, ckpt_every="rebuild")
+        c, g, h = gp.hvp(p.G, p.V)
+        out[precision] = (gp.last_fidelity, g, h)
+        gp.close()
+        del gp
+    F8, g8, h8 = out["c128"]
+    F4, g4, h4 = out["c64"]
+    e = np.einsum("kij,kij->k", np.conj(g8), p.G)
+    assert np.max(np.abs(e + 2 * F8)) <= 1e-10 * 2 * F8
+    eF = assert_fidelity(F4, F8, 1e-5, "n=30 c64 vs c128")
+    eg = assert_close(g4, g8, 1e-5, "n=30 c64 vs c128 grad")
+    eh = assert_close(h4, h8, 1e-5, "n=30 c64 vs c128 hvp")
+    print(f"n=30: F {F8:.3e}; c64 against c128: F {eF:.2e} grad {eg[0]:.2e}/{eg[1]:.2e} hvp {eh[0]:.2e}/{eh[1]:.2e}")
