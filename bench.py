@@ -468,7 +468,7 @@ def serving_sweep(n_req, rate_factors, seed):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (--gpus must be 1): the library has no multi-GPU path",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     if args.copy_probe:
