@@ -65,9 +65,11 @@ def test_tiny_config_vs_substitution_oracle(gpu, precision):
     _check(gp, ref, precision, p.G, p.V, "C1")
 
 
-@pytest.mark.parametrize("n,L,ns", [(2, 1, 3), (2, 4, 5), (3, 2, 4), (3, 5, 2), (4, 3, 7), (5, 6, 3),
-                                    (7, 3, 5), (8, 4, 2), (9, 5, 3), (10, 4, 3), (11, 3, 2), (12, 5, 3),
-                                    (13, 2, 2), (14, 3, 2)])
+SHAPES = [(2, 1, 3), (2, 4, 5), (3, 2, 4), (3, 5, 2), (4, 3, 7), (5, 6, 3), (7, 3, 5), (8, 4, 2), (9, 5, 3),
+          (10, 4, 3), (11, 3, 2), (12, 5, 3), (13, 2, 2), (14, 3, 2)]
+
+
+@pytest.mark.parametrize("n,L,ns", SHAPES)
 def test_shapes_c128(gpu, n, L, ns):
     """Every tile shape the planner makes: n below, at and above the tile size, odd and even n,
     several passes per layer, ragged sample counts."""
@@ -77,8 +79,9 @@ def test_shapes_c128(gpu, n, L, ns):
     _check(gp, ref, "c128", p.G, p.V, f"n={n} L={L}")
 
 
-@pytest.mark.parametrize("n,L,ns", [(5, 6, 3), (11, 3, 2), (14, 3, 2)])
+@pytest.mark.parametrize("n,L,ns", SHAPES)
 def test_shapes_c64(gpu, n, L, ns):
+    """The same shapes in complex64 (its own lane-bit choice per gate and its own LDS layout)."""
     p = make_problem(n, L, ns, seed=200 + n * 7 + L)
     ref = _oracle(p)
     gp = _gpu_problem(p, "c64")
