@@ -660,8 +660,10 @@ __global__ void __launch_bounds__(kThreads)
     x = (unsigned)deposit(it - s * tiles, pd.ibit, n - mb);
   }
 
-  // the next tile's loads are in flight while the current tile is computed
-  typename IO::V pf0[IO::NV], pf1[IO::NV];
+  // complex64: the next tile's loads are in flight while the current tile is computed, and a tile's
+  // stores wait until the next tile's loads are in; complex128 loads and stores at the tile's ends
+  // (the registers those take would halve its occupancy; the other workgroups on the CU cover it)
+  typename IO::V pf0[kF32 ? IO::NV : 1], pf1[kF32 ? IO::NV : 1];
 #define QHVP_FWD_PREFETCH(S, X)                                                                     \
   {                                                                                                 \
     const long long bn_ = (long long)(S) * dim + (X);                                               \
@@ -670,10 +672,12 @@ __global__ void __launch_bounds__(kThreads)
       if (TANG) pf1[v] = gld((const typename IO::V*)(srcD + bn_ + xv[v]));                          \
     }                                                                                               \
   }
-  if (!gen && c < nch) QHVP_FWD_PREFETCH(s, x);
+  if constexpr (kF32) {
+    if (!gen && c < nch) QHVP_FWD_PREFETCH(s, x);
+  }
   // The stores of tile t are issued after tile t+1's loads have been waited for: vmcnt counts
   // stores too, so stores issued right before that wait would be waited for as well.
-  typename IO::V st0[IO::NV], st1[IO::NV];
+  typename IO::V st0[kF32 ? IO::NV : 1], st1[kF32 ? IO::NV : 1];
   long long st_base = -1;
   StepRaw nxt;
   if constexpr (kF32) {
@@ -714,19 +718,35 @@ __global__ void __launch_bounds__(kThreads)
             if (TANG) sD[LD::at(t)] = cz<T>();
           }
         }
-    } else {
+    } else if constexpr (kF32) {
 #pragma unroll
       for (int v = 0; v < IO::NV; ++v) {
         IO::put(sP, IO::elem(tid, v), TS, pf0[v]);
         if (TANG) IO::put(sD, IO::elem(tid, v), TS, pf1[v]);
       }
+    } else {
+      typename IO::V l0[IO::NV], l1[IO::NV];
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v) {
+        l0[v] = gld((const typename IO::V*)(srcP + base + xv[v]));
+        if (TANG) l1[v] = gld((const typename IO::V*)(srcD + base + xv[v]));
+      }
+#pragma unroll
+      for (int v = 0; v < IO::NV; ++v) {
+        IO::put(sP, IO::elem(tid, v), TS, l0[v]);
+        if (TANG) IO::put(sD, IO::elem(tid, v), TS, l1[v]);
+      }
     }
-    if (st_base >= 0) {
-      if (stP) IO::write(dstP, st0, st_base, xv, TS, tid);
-      if (stD) IO::write(dstD, st1, st_base, xv, TS, tid);
+    if constexpr (kF32) {
+      if (st_base >= 0) {
+        if (stP) IO::write(dstP, st0, st_base, xv, TS, tid);
+        if (stD) IO::write(dstD, st1, st_base, xv, TS, tid);
+      }
     }
     __syncthreads();
-    if (!gen && hn) QHVP_FWD_PREFETCH(sn, xn);
+    if constexpr (kF32) {
+      if (!gen && hn) QHVP_FWD_PREFETCH(sn, xn);
+    }
 
     auto gate_step = [&](int j) {
       if constexpr (kF32) {
@@ -807,9 +827,14 @@ __global__ void __launch_bounds__(kThreads)
       }
     }
     if (stP || stD) {
-      if (stP) IO::read(st0, sP, tid);
-      if (stD) IO::read(st1, sD, tid);
-      st_base = base;
+      if constexpr (kF32) {
+        if (stP) IO::read(st0, sP, tid);
+        if (stD) IO::read(st1, sD, tid);
+        st_base = base;
+      } else {
+        if (stP) IO::store(dstP, sP, base, xv, TS, tid);
+        if (stD) IO::store(dstD, sD, base, xv, TS, tid);
+      }
     }
     if (firstt && tid == 0) sSch[1] = pend;
     __syncthreads();
@@ -830,14 +855,18 @@ __global__ void __launch_bounds__(kThreads)
         } else {
           s = it / tiles;
           x = (unsigned)deposit(it - s * tiles, pd.ibit, n - mb);
-          if (!gen) QHVP_FWD_PREFETCH(s, x);
+          if constexpr (kF32) {
+            if (!gen) QHVP_FWD_PREFETCH(s, x);
+          }
         }
       }
     }
   }
-  if (st_base >= 0) {
-    if (stP) IO::write(dstP, st0, st_base, xv, TS, tid);
-    if (stD) IO::write(dstD, st1, st_base, xv, TS, tid);
+  if constexpr (kF32) {
+    if (st_base >= 0) {
+      if (stP) IO::write(dstP, st0, st_base, xv, TS, tid);
+      if (stD) IO::write(dstD, st1, st_base, xv, TS, tid);
+    }
   }
 }
 
